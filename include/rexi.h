@@ -1,0 +1,177 @@
+/*
+ * rexi.h - C ABI of the MI355X (gfx950) T-REXI library for the linearised
+ * shallow-water equations on the rotating sphere.
+ *
+ * Method: Schreiber & Loft, "A Parallel Time-Integrator for Solving the
+ * Linearized Shallow Water Equations on the Rotating Sphere".  One time step
+ * applies the rational approximation of the exponential integrator
+ * (Section 4.2),
+ *     U_{n+1} ~ sum_k beta_k (alpha_k I + dt L)^{-1} U_n,
+ * to the linear operator L of Eq. (1) in spherical-harmonic space
+ * (Section 3), where L is block diagonal in the zonal order m (Section 5,
+ * Fig. 1) and every block is banded in the degree n.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Spectral layout.  Triangular truncation 0 <= m <= n <= T, only m >= 0
+ *   stored (m = 0 coefficients describe real fields).  Coefficients are
+ *   complex128 (interleaved re, im doubles) in m-major order,
+ *   idx(m, n) = m (T+1) - m (m-1)/2 + (n - m),  nspec = (T+1)(T+2)/2.
+ *   A state is [S][3][nspec] with the variables (Phi, vorticity, divergence)
+ *   in physical units (m^2/s^2, 1/s, 1/s).
+ * Basis.  Y_n^m = P_n^m(mu) e^{i m lam}, P_n^m orthonormal on [-1, 1]
+ *   (int P^2 dmu = 1), no Condon-Shortley phase, mu = sin(latitude)
+ *   (Section 3).
+ * Grid layout.  Real float64 [B][nlat][nlon]; latitude row 0 is the
+ *   northernmost Gauss-Legendre latitude, lam_k = 2 pi k / nlon.
+ * REXI sign convention.  The pole list alpha_k = h (mu + i k),
+ *   k = -(M+L)..(M+L), and the two weight lists beta+_k, beta-_k satisfy
+ *       e^{z} ~ sum_k beta+_k / (z + alpha_k) + sum_k beta-_k / (alpha_k - z)
+ *   for z = i x on the covered range (Section 4.1), so one step is
+ *       u1 = sum_k beta+_k (alpha_k + dt L)^{-1} u0 + sum_k beta-_k (alpha_k - dt L)^{-1} u0.
+ *   (The same list written as (alpha'_k I - dt L) u_k = u0 uses
+ *   alpha' in {-alpha_k} u {alpha_k} with beta' in {-beta+_k} u {beta-_k}.)
+ * Memory.  Pointers documented "device" must be device memory of the
+ *   current HIP device (e.g. torch tensors), contiguous; "host" pointers are
+ *   plain host memory.  The caller owns every buffer it passes; the plan owns
+ *   its tables, workspace and captured graphs.  Outputs must not overlap
+ *   inputs (REXI_EALIAS).
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Calls enqueue work and return; argument errors are reported
+ *   synchronously, errors of enqueued work by the next call or at
+ *   synchronisation.
+ * Threads.  A plan may be used from one thread at a time.  Calls on one plan
+ *   share its workspace: calls that overlap on different streams race.
+ * Errors.  Every int-returning call returns REXI_OK (0) or a negative code;
+ *   rexi_last_error() then describes the failure (thread-local string).
+ */
+#ifndef REXI_H
+#define REXI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    REXI_OK = 0,
+    REXI_EINVAL = -1,        /* bad argument (size, pointer, parameter range) */
+    REXI_ENOMEM = -2,        /* device or host allocation failed */
+    REXI_EHIP = -3,          /* a HIP runtime call failed */
+    REXI_EUNSUPPORTED = -4,  /* valid but not supported (e.g. size above plan limits) */
+    REXI_EALIAS = -5         /* output overlaps input */
+};
+
+/* Opaque plan: tables, schedule, workspace and graphs for one configuration. */
+typedef struct rexi_plan rexi_plan;
+
+/* Parameters of a plan.
+ *   T                 truncation (1 <= T <= 1023)
+ *   nlat, nlon        Gaussian grid of the transforms (nlat >= 2, nlon a power of
+ *                     two, 4 <= nlon <= 4096, T < nlon); 0, 0 = no transforms
+ *   radius, omega, gravity, mean_depth
+ *                     planet radius a (m), rotation rate Omega (1/s), g (m/s^2),
+ *                     mean depth H (m); Phibar = g H (Eq. (1), Section 6)
+ *   dt                time step (s), > 0
+ *   M, h, L           REXI: Gaussians per side, Gaussian width, half-width K of
+ *                     the rational basis (Section 4.1); M >= 1, 0 < h, 1 <= L <= 32
+ *   normalize         1: divide beta by the x = 0 response (Section 6.1), 0: raw
+ *   max_states        largest S accepted by rexi_step / rexi_step_adjoint
+ *   max_fields        largest B accepted by sh_forward / sh_inverse */
+typedef struct rexi_params {
+    int T;
+    int nlat, nlon;
+    double radius, omega, gravity, mean_depth;
+    double dt;
+    int M;
+    double h;
+    int L;
+    int normalize;
+    int max_states;
+    int max_fields;
+} rexi_params;
+
+/* REXI poles and weights (Section 4.1; renormalisation of Section 6.1).
+ * Fits the Gaussian psi(y) = (4 pi)^{-1/2} e^{-y^2/4} by
+ * Re sum_{l=-L}^{L} a_l / (i y + mu + i l) with a_{-l} = conj(a_l)
+ * (least squares, mu chosen by a scan), forms the Gaussian sum
+ * b_m = e^{h^2} e^{-i m h}, m = -M..M, and merges both into the two-sided
+ * list described above.  Host only; no GPU needed.
+ *   capacity   number of complex entries the three output arrays can hold;
+ *              0 = only report the count in *n_poles (arrays may be NULL)
+ *   alpha, beta_plus, beta_minus
+ *              host, 2*capacity doubles each (re, im interleaved), pole index
+ *              k = -(M+L)..(M+L) stored at position k + M + L
+ *   n_poles    host, receives N = 2 (M + L) + 1
+ * Returns REXI_EINVAL for M < 1, h <= 0, L < 1 or L > 32, or
+ * capacity in (0, N); REXI_OK otherwise. */
+int rexi_coeffs(int M, double h, int L, int normalize, int capacity,
+                double *alpha, double *beta_plus, double *beta_minus, int *n_poles);
+
+/* Build a plan: coefficients, per-(n, m) operator constants in energy
+ * variables, Gauss-Legendre nodes and Legendre tables, work schedule and
+ * device workspace for up to max_states states / max_fields fields.
+ * p: host; *out receives the plan.  Uses the current HIP device. */
+int rexi_plan_create(const rexi_params *p, rexi_plan **out);
+
+/* Release a plan and everything it owns (synchronises the device first). */
+int rexi_plan_destroy(rexi_plan *plan);
+
+/* Plan facts: N (poles), nspec, and the number of (pole, m) blocks per step,
+ * N (T+1).  Any pointer may be NULL. */
+int rexi_plan_info(const rexi_plan *plan, int *n_poles, int *nspec, long long *blocks_per_step);
+
+/* Copy the plan's pole list to host arrays of 2N doubles each (same layout
+ * as rexi_coeffs). */
+int rexi_plan_coeffs(const rexi_plan *plan, double *alpha, double *beta_plus, double *beta_minus);
+
+/* Spherical-harmonic analysis (Section 3): grid -> spectral.
+ * xi_n^m = sum_j w_j P_n^m(mu_j) (1/nlon) sum_k xi(mu_j, lam_k) e^{-i m lam_k}
+ *   grid  device float64 [B][nlat][nlon]
+ *   spec  device complex128 [B][nspec]
+ *   1 <= B <= max_fields.  Exact inverse of sh_inverse for n < nlat and
+ *   m < nlon/2; beyond that the quadrature / Nyquist limits apply. */
+int sh_forward(rexi_plan *plan, const double *grid, void *spec, int B, void *stream);
+
+/* Spherical-harmonic synthesis (Section 3): spectral -> grid.
+ * xi = sum_n Re(xi_n^0) P_n^0 + 2 Re sum_{m>0} sum_n xi_n^m P_n^m e^{i m lam}
+ *   spec  device complex128 [B][nspec];  grid  device float64 [B][nlat][nlon] */
+int sh_inverse(rexi_plan *plan, const void *spec, double *grid, int B, void *stream);
+
+/* nsteps T-REXI steps (Section 4.2, Algorithm 1's sum and reduction) of S
+ * states: u1 = R^nsteps u0 with
+ *   R = sum_k beta+_k (alpha_k + dt L)^{-1} + sum_k beta-_k (alpha_k - dt L)^{-1}.
+ *   u0, u1  device complex128 [S][3][nspec] (must not overlap)
+ *   1 <= S <= max_states, nsteps >= 0 (0 copies u0 to u1). */
+int rexi_step(rexi_plan *plan, const void *u0, void *u1, int S, int nsteps, void *stream);
+
+/* Adjoint of rexi_step: g0 = (R^H)^nsteps g1, the conjugate-transposed
+ * shifted solves with conjugated weights.  For a real loss of u1 with
+ * gradient g1 = dL/dRe(u1) + i dL/dIm(u1), g0 is the same gradient for u0.
+ * Arguments as rexi_step. */
+int rexi_step_adjoint(rexi_plan *plan, const void *g1, void *g0, int S, int nsteps, void *stream);
+
+/* One forward step in the plain per-term form: one launch per pole k that
+ * solves every m-block of (alpha_k +- dt L) and accumulates into a device
+ * accumulator, then a final conversion.  Same arithmetic and result as
+ * rexi_step with nsteps = 1 (to rounding); kept as the comparison point for
+ * the batched form.  Arguments as rexi_step. */
+int rexi_step_per_term(rexi_plan *plan, const void *u0, void *u1, int S, void *stream);
+
+/* Time the candidate tile/wave schedules for S states on `stream` (runs
+ * steps on internal buffers) and keep the fastest for later calls with S.
+ * *chosen (may be NULL) receives the index of the chosen candidate. */
+int rexi_plan_autotune(rexi_plan *plan, int S, void *stream, int *chosen);
+
+/* Select schedule candidate `index` (as reported by rexi_plan_autotune) for
+ * S states; REXI_EINVAL if out of range.  *count (may be NULL) receives the
+ * number of candidates. */
+int rexi_plan_set_schedule(rexi_plan *plan, int S, int index, int *count);
+
+/* Description of the last non-zero return on this thread ("" if none). */
+const char *rexi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REXI_H */

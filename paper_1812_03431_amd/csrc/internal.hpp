@@ -1,0 +1,137 @@
+// Internal declarations shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/rexi.h"
+
+namespace rexi {
+
+using cld = std::complex<long double>;
+
+// ---------------------------------------------------------------- errors
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define REXI_HIP(call)                                            \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::rexi::hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- host math
+// Gaussian rational fit (Section 4.1): mu and a_l, l = -L..L.
+struct GaussFit {
+    long double mu;
+    std::vector<cld> a;  // size 2L+1, index l + L
+    double max_err;
+};
+GaussFit fit_gaussian(int L);
+
+// Two-sided REXI list (see rexi.h).  Index k + M + L for k = -(M+L)..(M+L).
+struct Poles {
+    std::vector<std::complex<double>> alpha, beta_plus, beta_minus;
+};
+Poles make_poles(int M, double h, int L, int normalize);
+
+// Gauss-Legendre nodes (descending, north to south) and weights.
+void gauss_legendre(int nlat, std::vector<double>& mu, std::vector<double>& w);
+
+// Orthonormal P_n^m(mu_j): returned as [m][n-m][j] packed by m-blocks,
+// block m at offset spec_offset(T, m) * nlat.
+std::vector<double> legendre_table(int T, const std::vector<double>& mu);
+
+__host__ __device__ inline long long spec_offset(int T, int m) {
+    return (long long)m * (T + 1) - (long long)m * (m - 1) / 2;
+}
+__host__ __device__ inline long long nspec_of(int T) { return (long long)(T + 1) * (T + 2) / 2; }
+
+// ---------------------------------------------------------------- device-side structs
+// Per zonal order m: the two parity chains of the Phi-eliminated block.
+//   chain p holds vorticity at degrees n == p (mod 2) and divergence at the
+//   others; Phi_n is carried with the divergence element of degree n.
+//   n0 = max(m, 1) (the (0,0) mode is handled on its own), L = T + 1 - n0.
+//   P lanes per chain problem (a power of two), s elements per lane.
+struct MInfo {
+    int n0, L, P, s;
+    int spec_off;   // idx(m, m)
+    int slot_base;  // first chain slot of this m (chain p at slot_base + p L)
+};
+
+// One work item of the fused solve: chain p of order m, states
+// [tile*ST, tile*ST + ST), poles [k0, k1).  Its partial sums go to
+// part + part_off (complex units), layout [ST][2][L].
+struct Item {
+    int m, p, tile, k0, k1;
+    long long part_off;
+};
+
+// Per (m, p, tile): where its nr partials start (consecutive items).
+struct Group {
+    long long part_off;
+    int nr;
+    int pad;
+};
+
+struct Schedule {
+    int SM = 4;       // elements per lane (template)
+    int ST = 1;       // states per wave (template)
+    int S = 0;        // states this schedule serves
+    std::vector<MInfo> minfo;
+    std::vector<Item> items;
+    std::vector<Group> groups;  // index ((m * 2 + p) * ntiles + tile)
+    long long part_size = 0;    // complex entries
+    // device copies
+    MInfo* d_minfo = nullptr;
+    Item* d_items = nullptr;
+    Group* d_groups = nullptr;
+    std::string name;
+};
+
+}  // namespace rexi
+
+// ---------------------------------------------------------------- the plan
+struct rexi_plan {
+    rexi_params prm;
+    int T = 0, N = 0;
+    long long nspec = 0, nslots = 0;
+    double phibar = 0;
+    rexi::Poles poles;
+    std::complex<double> g00_fwd, g00_adj, gphi_fwd, gphi_adj;
+
+    // per-(n, m) constants in spectral order (device)
+    double *d_th = nullptr, *d_om = nullptr, *d_cc = nullptr, *d_sc = nullptr;
+    int *d_idx_n = nullptr, *d_idx_m = nullptr;
+    // poles for forward and adjoint weights (device, double2)
+    double2 *d_alpha = nullptr, *d_ainv = nullptr;
+    double2 *d_wx[2] = {nullptr, nullptr}, *d_wy[2] = {nullptr, nullptr};
+    double2 *d_wxa[2] = {nullptr, nullptr}, *d_wya[2] = {nullptr, nullptr};
+    // workspace (sized for max_states)
+    double2 *d_ch_var[2] = {nullptr, nullptr};  // [S][nslots + 2]
+    double2 *d_ch_phi[2] = {nullptr, nullptr};  // [S][nspec]
+    double2 *d_part = nullptr;
+    long long part_capacity = 0;
+    double2 *d_acc = nullptr;                    // per-term form accumulator [S][2][nslots]
+    // chain-slot layout (device) and slot -> m table
+    rexi::MInfo* sched_layout = nullptr;
+    int* d_slot_m = nullptr;
+    // schedules: candidates per S, chosen index per S; per-term form per S
+    std::vector<std::vector<rexi::Schedule>> sched;  // [S] -> candidates
+    std::vector<int> chosen;
+    std::vector<rexi::Schedule> per_term;             // [S]
+    long long acc_capacity = 0;
+
+    // transforms
+    int nlat = 0, nlon = 0, nhalf = 0;
+    std::vector<double> mu, w;
+    double* d_plm = nullptr;      // Legendre table for the transforms
+    double* d_wts = nullptr;      // Gauss weights
+    double* d_four = nullptr;     // Fourier coefficients workspace [T+1][nlat][2B]
+    double2* d_twiddle = nullptr; // FFT twiddles
+    void* d_tiles_f = nullptr;    // Legendre tiles, forward / inverse
+    void* d_tiles_i = nullptr;
+    int ntiles_f = 0, ntiles_i = 0;
+};

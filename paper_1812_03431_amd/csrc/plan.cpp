@@ -1,0 +1,613 @@
+// C ABI of the T-REXI library: argument checking, plans, schedules, step
+// drivers and the schedule autotuner.  The arithmetic runs in the HIP kernels
+// (rexi_kernels.hip, sh_kernels.hip); this file only prepares tables and
+// enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace rexi {
+
+bool solve_variant_supported(int SM, int ST);
+hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
+                        hipStream_t s);
+hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int adjoint, hipStream_t s);
+hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,
+                          void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s);
+hipError_t enqueue_zero(double2* p, long long n, hipStream_t s);
+hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int buf, int S, hipStream_t s);
+int sh_setup(rexi_plan* pl);
+void sh_release(rexi_plan* pl);
+int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStream_t s);
+
+namespace {
+thread_local std::string g_err;
+}
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(REXI_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+template <class T>
+int dev_alloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(REXI_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                     " bytes failed: " + hipGetErrorString(e));
+    }
+    return REXI_OK;
+}
+
+template <class T>
+int upload(T** p, const std::vector<T>& v) {
+    int rc = dev_alloc(p, v.size());
+    if (rc) return rc;
+    REXI_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return REXI_OK;
+}
+
+template <class T>
+void dev_free(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+int check_params(const rexi_params* p) {
+    if (!p) return fail(REXI_EINVAL, "params is NULL");
+    if (p->T < 1 || p->T > 1023) return fail(REXI_EINVAL, "T must be in [1, 1023]");
+    if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(REXI_EINVAL, "dt must be positive and finite");
+    if (!(p->radius > 0) || !(p->gravity > 0) || !(p->mean_depth > 0) || !std::isfinite(p->omega))
+        return fail(REXI_EINVAL, "radius, gravity and mean_depth must be positive, omega finite");
+    if (p->M < 1 || p->M > 1 << 20) return fail(REXI_EINVAL, "M must be in [1, 2^20]");
+    if (!(p->h > 0) || !std::isfinite(p->h)) return fail(REXI_EINVAL, "h must be positive");
+    if (p->L < 1 || p->L > 32) return fail(REXI_EINVAL, "L must be in [1, 32]");
+    if (p->max_states < 1 || p->max_states > 64) return fail(REXI_EINVAL, "max_states must be in [1, 64]");
+    if (p->nlat != 0 || p->nlon != 0) {
+        if (p->nlat < 2 || p->nlat > 4096) return fail(REXI_EINVAL, "nlat must be in [2, 4096]");
+        if (p->nlon < 4 || p->nlon > 4096 || (p->nlon & (p->nlon - 1)))
+            return fail(REXI_EINVAL, "nlon must be a power of two in [4, 4096]");
+        if (p->T >= p->nlon) return fail(REXI_EINVAL, "T must be below nlon");
+        if (p->max_fields < 1 || p->max_fields > 1024) return fail(REXI_EINVAL, "max_fields must be in [1, 1024]");
+    }
+    return REXI_OK;
+}
+
+long double eps_nm(int n, int m) {
+    if (n <= 0 || n < m) return 0.0L;
+    return sqrtl((long double)((long long)n * n - (long long)m * m) / (4.0L * n * n - 1.0L));
+}
+
+// Layout of the chain slots (independent of the lane tiling).
+std::vector<MInfo> chain_layout(int T) {
+    std::vector<MInfo> mi(T + 1);
+    long long slot = 0;
+    for (int m = 0; m <= T; ++m) {
+        MInfo x{};
+        x.n0 = std::max(m, 1);
+        x.L = T + 1 - x.n0;
+        x.spec_off = (int)spec_offset(T, m);
+        x.slot_base = (int)slot;
+        slot += 2LL * x.L;
+        mi[m] = x;
+    }
+    return mi;
+}
+
+// Work split of one candidate schedule.  Cost model per wave iteration
+// (64/P poles of one chain): s elements x (factorisation + 2 ST right-hand
+// sides) plus log2(P) cyclic-reduction levels.
+int build_schedule(rexi_plan* pl, int S, int SM, int ST, long long target_items, bool per_term, Schedule& out) {
+    const int T = pl->T, N = per_term ? 1 : pl->N;
+    out = Schedule();
+    out.SM = SM;
+    out.ST = ST;
+    out.S = S;
+    out.minfo = chain_layout(T);
+    const int ntiles = (S + ST - 1) / ST;
+    struct Unit { int m, p, tile; double cost; int iters; int G; };
+    std::vector<Unit> units;
+    double total = 0;
+    for (int m = 0; m <= T; ++m) {
+        MInfo& mi = out.minfo[m];
+        int P = 1;
+        while (P * SM < mi.L) P *= 2;
+        if (P > 64) return fail(REXI_EUNSUPPORTED, "chain too long for this tiling");
+        int s = (mi.L + P - 1) / P;
+        if (s < 2) s = 2;
+        mi.P = P;
+        mi.s = s;
+        const int G = 64 / P;
+        int lg = 0;
+        while ((1 << lg) < P) ++lg;
+        const double it_cost = s * (36.0 + 2 * ST * 40.0) + lg * (36.0 + 2 * ST * 8.0) + 20.0;
+        const int iters = (N + G - 1) / G;
+        for (int p = 0; p < 2; ++p)
+            for (int t = 0; t < ntiles; ++t) {
+                units.push_back({m, p, t, it_cost * iters, iters, G});
+                total += it_cost * iters;
+            }
+    }
+    const double target = per_term ? 1e300 : total / (double)std::max<long long>(1, target_items);
+    out.groups.assign((size_t)(T + 1) * 2 * ntiles, Group{0, 0, 0});
+    long long off = 0;
+    std::vector<std::pair<double, Item>> items;
+    for (const Unit& u : units) {
+        int nr = (int)std::lround(u.cost / target);
+        nr = std::max(1, std::min(nr, u.iters));
+        const long long sz = (long long)ST * 2 * out.minfo[u.m].L;
+        Group& gr = out.groups[((size_t)u.m * 2 + u.p) * ntiles + u.tile];
+        gr.part_off = off;
+        gr.nr = nr;
+        for (int r = 0; r < nr; ++r) {
+            const int i0 = (int)((long long)u.iters * r / nr), i1 = (int)((long long)u.iters * (r + 1) / nr);
+            Item it;
+            it.m = u.m;
+            it.p = u.p;
+            it.tile = u.tile;
+            it.k0 = i0 * u.G;
+            it.k1 = std::min(N, i1 * u.G);
+            it.part_off = off;
+            off += sz;
+            items.push_back({u.cost * (i1 - i0) / u.iters, it});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<double, Item>& a, const std::pair<double, Item>& b) { return a.first > b.first; });
+    for (auto& x : items) out.items.push_back(x.second);
+    out.part_size = off;
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "SM%d_ST%d_items%lld%s", SM, ST, (long long)out.items.size(),
+                  per_term ? "_perterm" : "");
+    out.name = buf;
+    int rc = upload(&out.d_minfo, out.minfo);
+    if (!rc) rc = upload(&out.d_items, out.items);
+    if (!rc) rc = upload(&out.d_groups, out.groups);
+    return rc;
+}
+
+void free_schedule(Schedule& s) {
+    dev_free(s.d_minfo);
+    dev_free(s.d_items);
+    dev_free(s.d_groups);
+}
+
+int ensure_part(rexi_plan* pl, long long n) {
+    if (n <= pl->part_capacity) return REXI_OK;
+    dev_free(pl->d_part);
+    pl->part_capacity = 0;
+    int rc = dev_alloc(&pl->d_part, (size_t)n);
+    if (rc) return rc;
+    pl->part_capacity = n;
+    return REXI_OK;
+}
+
+// Candidate schedules for S states (built on first use).
+int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
+    if ((int)pl->sched.size() <= S) {
+        pl->sched.resize(S + 1);
+        pl->chosen.resize(S + 1, -1);
+    }
+    std::vector<Schedule>& c = pl->sched[S];
+    if (c.empty()) {
+        const int sms[] = {4, 8};
+        const int sts[] = {1, 2, 4};
+        const long long tg[] = {2048, 8192, 32768};
+        for (int SM : sms)
+            for (int ST : sts) {
+                if (!solve_variant_supported(SM, ST)) continue;
+                if (ST > S && ST > 1) continue;
+                for (long long t : tg) {
+                    Schedule sc;
+                    int rc = build_schedule(pl, S, SM, ST, t, false, sc);
+                    if (rc == REXI_EUNSUPPORTED) { free_schedule(sc); continue; }
+                    if (rc) { free_schedule(sc); return rc; }
+                    rc = ensure_part(pl, sc.part_size);
+                    if (rc) { free_schedule(sc); return rc; }
+                    c.push_back(sc);
+                }
+            }
+        if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
+        // default: SM 4, the largest state tile that divides the work, 8192 items
+        int best = 0;
+        for (int i = 0; i < (int)c.size(); ++i) {
+            const Schedule& s = c[i];
+            const int want_st = S >= 2 ? 2 : 1;
+            if (s.SM == 4 && s.ST == want_st && s.name.find("items") != std::string::npos) {
+                best = i;
+                if (s.items.size() >= 4096) break;
+            }
+        }
+        pl->chosen[S] = best;
+    }
+    *out = &c;
+    return REXI_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+int check_state_call(rexi_plan* pl, const void* in, const void* out, int S, int nsteps) {
+    if (!pl) return fail(REXI_EINVAL, "plan is NULL");
+    if (!in || !out) return fail(REXI_EINVAL, "state pointer is NULL");
+    if (S < 1) return fail(REXI_EINVAL, "S must be >= 1");
+    if (S > pl->prm.max_states) return fail(REXI_EUNSUPPORTED, "S exceeds the plan's max_states");
+    if (nsteps < 0) return fail(REXI_EINVAL, "nsteps must be >= 0");
+    const size_t bytes = (size_t)S * 3 * pl->nspec * 16;
+    if (overlaps(in, bytes, out, bytes)) return fail(REXI_EALIAS, "output overlaps input");
+    return REXI_OK;
+}
+
+int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S, int nsteps, int adjoint,
+              hipStream_t s) {
+    const size_t bytes = (size_t)S * 3 * pl->nspec * 16;
+    if (nsteps == 0) {
+        REXI_HIP(hipMemcpyAsync(u1, u0, bytes, hipMemcpyDeviceToDevice, s));
+        return REXI_OK;
+    }
+    REXI_HIP(enqueue_prep(pl, u0, 0, S, adjoint, pl->sched_layout, s));
+    int cur = 0;
+    for (int k = 0; k < nsteps; ++k) {
+        const bool last = (k == nsteps - 1);
+        REXI_HIP(enqueue_solve(pl, sc, cur, S, adjoint, s));
+        REXI_HIP(enqueue_reduce(pl, sc, pl->d_part, cur, cur ^ 1, last ? u1 : nullptr, S, adjoint, pl->d_slot_m, s));
+        cur ^= 1;
+    }
+    return REXI_OK;
+}
+
+}  // namespace
+}  // namespace rexi
+
+using namespace rexi;
+
+namespace {
+
+int do_step(rexi_plan* pl, const void* u0, void* u1, int S, int nsteps, int adjoint, void* stream) {
+    int rc = check_state_call(pl, u0, u1, S, nsteps);
+    if (rc) return rc;
+    std::vector<Schedule>* c = nullptr;
+    rc = schedules_for(pl, S, &c);
+    if (rc) return rc;
+    return run_steps(pl, (*c)[pl->chosen[S]], u0, u1, S, nsteps, adjoint, (hipStream_t)stream);
+}
+
+void release(rexi_plan* pl) {
+    for (auto& c : pl->sched)
+        for (auto& s : c) free_schedule(s);
+    for (auto& s : pl->per_term) free_schedule(s);
+    dev_free(pl->d_th);
+    dev_free(pl->d_om);
+    dev_free(pl->d_cc);
+    dev_free(pl->d_sc);
+    dev_free(pl->d_idx_n);
+    dev_free(pl->d_idx_m);
+    dev_free(pl->d_alpha);
+    dev_free(pl->d_ainv);
+    for (int d = 0; d < 2; ++d) {
+        dev_free(pl->d_wx[d]);
+        dev_free(pl->d_wy[d]);
+        dev_free(pl->d_wxa[d]);
+        dev_free(pl->d_wya[d]);
+        dev_free(pl->d_ch_var[d]);
+        dev_free(pl->d_ch_phi[d]);
+    }
+    dev_free(pl->d_part);
+    dev_free(pl->d_acc);
+    dev_free(pl->sched_layout);
+    dev_free(pl->d_slot_m);
+    sh_release(pl);
+}
+
+std::vector<double2> to_d2(const std::vector<std::complex<double>>& v) {
+    std::vector<double2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2(v[i].real(), v[i].imag());
+    return o;
+}
+
+int create(const rexi_params* p, rexi_plan** out) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    rexi_plan* pl = new rexi_plan();
+    pl->prm = *p;
+    const int T = p->T;
+    pl->T = T;
+    pl->N = 2 * (p->M + p->L) + 1;
+    pl->nspec = nspec_of(T);
+    pl->nslots = 2 * (pl->nspec - 1);
+    pl->phibar = p->gravity * p->mean_depth;
+    pl->poles = make_poles(p->M, p->h, p->L, p->normalize);
+    const int N = pl->N;
+    typedef std::complex<double> C;
+    std::vector<C> ainv(N), wx[2], wy[2], wxa[2], wya[2];
+    for (int d = 0; d < 2; ++d) {
+        wx[d].resize(N);
+        wy[d].resize(N);
+        wxa[d].resize(N);
+        wya[d].resize(N);
+    }
+    C g00(0, 0), gx[2] = {C(0, 0), C(0, 0)}, gy[2] = {C(0, 0), C(0, 0)};
+    for (int k = 0; k < N; ++k) {
+        const C a = pl->poles.alpha[k];
+        ainv[k] = 1.0 / a;
+        const C bp = pl->poles.beta_plus[k];
+        const C bm_mirror = std::conj(pl->poles.beta_minus[N - 1 - k]);  // conj(beta-_{-k})
+        wx[0][k] = bp;
+        wy[0][k] = bm_mirror;
+        wx[1][k] = bm_mirror;
+        wy[1][k] = bp;
+        for (int d = 0; d < 2; ++d) {
+            wxa[d][k] = wx[d][k] / a;
+            wya[d][k] = wy[d][k] / a;
+            gx[d] += wxa[d][k];
+            gy[d] += wya[d][k];
+        }
+        g00 += (pl->poles.beta_plus[k] + pl->poles.beta_minus[k]) / a;
+    }
+    pl->g00_fwd = g00;
+    pl->g00_adj = std::conj(g00);
+    pl->gphi_fwd = gx[0] + std::conj(gy[0]);
+    pl->gphi_adj = gx[1] + std::conj(gy[1]);
+
+    // per-(n, m) constants of the energy-scaled operator (times dt)
+    const long long ns = pl->nspec;
+    std::vector<double> th(ns), om(ns), cc(ns), sc(ns);
+    std::vector<int> in(ns), im(ns);
+    const long double a = p->radius, Om = p->omega, pb = pl->phibar, dt = p->dt;
+    for (int m = 0; m <= T; ++m)
+        for (int n = m; n <= T; ++n) {
+            const long long i = spec_offset(T, m) + (n - m);
+            in[i] = n;
+            im[i] = m;
+            if (n == 0) {
+                th[i] = om[i] = cc[i] = 0.0;
+                sc[i] = 1.0;
+                continue;
+            }
+            const long double nn = (long double)n * (n + 1);
+            th[i] = (double)(2 * Om * m / nn * dt);
+            om[i] = (double)(sqrtl(pb * nn) / a * dt);
+            const long double kap = eps_nm(n, m) * sqrtl((long double)n * n - 1) / n;
+            cc[i] = (double)(2 * Om * dt * kap);
+            sc[i] = (double)(a * sqrtl(pb / nn));
+        }
+    std::vector<MInfo> lay = chain_layout(T);
+    std::vector<int> slot_m(pl->nslots);
+    for (int m = 0; m <= T; ++m)
+        for (int q = 0; q < 2 * lay[m].L; ++q) slot_m[lay[m].slot_base + q] = m;
+
+    rc = upload(&pl->d_th, th);
+    if (!rc) rc = upload(&pl->d_om, om);
+    if (!rc) rc = upload(&pl->d_cc, cc);
+    if (!rc) rc = upload(&pl->d_sc, sc);
+    if (!rc) rc = upload(&pl->d_idx_n, in);
+    if (!rc) rc = upload(&pl->d_idx_m, im);
+    if (!rc) rc = upload(&pl->d_alpha, to_d2(pl->poles.alpha));
+    if (!rc) rc = upload(&pl->d_ainv, to_d2(ainv));
+    for (int d = 0; d < 2 && !rc; ++d) {
+        rc = upload(&pl->d_wx[d], to_d2(wx[d]));
+        if (!rc) rc = upload(&pl->d_wy[d], to_d2(wy[d]));
+        if (!rc) rc = upload(&pl->d_wxa[d], to_d2(wxa[d]));
+        if (!rc) rc = upload(&pl->d_wya[d], to_d2(wya[d]));
+    }
+    if (!rc) rc = upload(&pl->sched_layout, lay);
+    if (!rc) rc = upload(&pl->d_slot_m, slot_m);
+    for (int d = 0; d < 2 && !rc; ++d) {
+        rc = dev_alloc(&pl->d_ch_var[d], (size_t)p->max_states * (pl->nslots + 2));
+        if (!rc) rc = dev_alloc(&pl->d_ch_phi[d], (size_t)p->max_states * pl->nspec);
+    }
+    if (!rc && p->nlat > 0) rc = sh_setup(pl);
+    if (rc) {
+        release(pl);
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return REXI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rexi_last_error(void) { return g_err.c_str(); }
+
+int rexi_coeffs(int M, double h, int L, int normalize, int capacity, double* alpha, double* beta_plus,
+                double* beta_minus, int* n_poles) {
+    try {
+        g_err.clear();
+        if (M < 1 || M > 1 << 20) return fail(REXI_EINVAL, "M must be in [1, 2^20]");
+        if (!(h > 0) || !std::isfinite(h)) return fail(REXI_EINVAL, "h must be positive");
+        if (L < 1 || L > 32) return fail(REXI_EINVAL, "L must be in [1, 32]");
+        if (capacity < 0) return fail(REXI_EINVAL, "capacity must be >= 0");
+        const int N = 2 * (M + L) + 1;
+        if (n_poles) *n_poles = N;
+        if (capacity == 0) return REXI_OK;
+        if (capacity < N) return fail(REXI_EINVAL, "capacity below the number of poles");
+        if (!alpha || !beta_plus || !beta_minus) return fail(REXI_EINVAL, "output array is NULL");
+        const Poles P = make_poles(M, h, L, normalize);
+        for (int k = 0; k < N; ++k) {
+            alpha[2 * k] = P.alpha[k].real();
+            alpha[2 * k + 1] = P.alpha[k].imag();
+            beta_plus[2 * k] = P.beta_plus[k].real();
+            beta_plus[2 * k + 1] = P.beta_plus[k].imag();
+            beta_minus[2 * k] = P.beta_minus[k].real();
+            beta_minus[2 * k + 1] = P.beta_minus[k].imag();
+        }
+        return REXI_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(REXI_ENOMEM, "host allocation failed");
+    }
+}
+
+int rexi_plan_create(const rexi_params* p, rexi_plan** out) {
+    if (!out) return fail(REXI_EINVAL, "out is NULL");
+    *out = nullptr;
+    try {
+        return create(p, out);
+    } catch (const std::bad_alloc&) {
+        return fail(REXI_ENOMEM, "host allocation failed");
+    }
+}
+
+int rexi_plan_destroy(rexi_plan* plan) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    release(plan);
+    delete plan;
+    return REXI_OK;
+}
+
+int rexi_plan_info(const rexi_plan* plan, int* n_poles, int* nspec, long long* blocks) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (n_poles) *n_poles = plan->N;
+    if (nspec) *nspec = (int)plan->nspec;
+    if (blocks) *blocks = (long long)plan->N * (plan->T + 1);
+    return REXI_OK;
+}
+
+int rexi_plan_coeffs(const rexi_plan* plan, double* alpha, double* beta_plus, double* beta_minus) {
+    if (!plan || !alpha || !beta_plus || !beta_minus) return fail(REXI_EINVAL, "NULL argument");
+    for (int k = 0; k < plan->N; ++k) {
+        alpha[2 * k] = plan->poles.alpha[k].real();
+        alpha[2 * k + 1] = plan->poles.alpha[k].imag();
+        beta_plus[2 * k] = plan->poles.beta_plus[k].real();
+        beta_plus[2 * k + 1] = plan->poles.beta_plus[k].imag();
+        beta_minus[2 * k] = plan->poles.beta_minus[k].real();
+        beta_minus[2 * k + 1] = plan->poles.beta_minus[k].imag();
+    }
+    return REXI_OK;
+}
+
+int rexi_step(rexi_plan* plan, const void* u0, void* u1, int S, int nsteps, void* stream) {
+    try {
+        return do_step(plan, u0, u1, S, nsteps, 0, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(REXI_ENOMEM, "host allocation failed");
+    }
+}
+
+int rexi_step_adjoint(rexi_plan* plan, const void* g1, void* g0, int S, int nsteps, void* stream) {
+    try {
+        return do_step(plan, g1, g0, S, nsteps, 1, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(REXI_ENOMEM, "host allocation failed");
+    }
+}
+
+int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* stream) {
+    int rc = check_state_call(plan, u0, u1, S, 1);
+    if (rc) return rc;
+    try {
+        if ((int)plan->per_term.size() <= S) plan->per_term.resize(S + 1);
+        Schedule& sc = plan->per_term[S];
+        if (sc.items.empty()) {
+            rc = build_schedule(plan, S, 4, 1, 0, true, sc);
+            if (rc) { free_schedule(sc); sc = Schedule(); return rc; }
+        }
+        if (sc.part_size > plan->acc_capacity) {
+            dev_free(plan->d_acc);
+            plan->acc_capacity = 0;
+            rc = dev_alloc(&plan->d_acc, (size_t)sc.part_size);
+            if (rc) return rc;
+            plan->acc_capacity = sc.part_size;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        REXI_HIP(enqueue_prep(plan, u0, 0, S, 0, plan->sched_layout, s));
+        REXI_HIP(enqueue_zero(plan->d_acc, sc.part_size, s));
+        for (int k = 0; k < plan->N; ++k) REXI_HIP(enqueue_per_term_pole(plan, sc, k, 0, S, s));
+        REXI_HIP(enqueue_reduce(plan, sc, plan->d_acc, 0, 1, u1, S, 0, plan->d_slot_m, s));
+        return REXI_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(REXI_ENOMEM, "host allocation failed");
+    }
+}
+
+int rexi_plan_set_schedule(rexi_plan* plan, int S, int index, int* count) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
+    std::vector<Schedule>* c = nullptr;
+    int rc = schedules_for(plan, S, &c);
+    if (rc) return rc;
+    if (count) *count = (int)c->size();
+    if (index < 0) return REXI_OK;
+    if (index >= (int)c->size()) return fail(REXI_EINVAL, "schedule index out of range");
+    plan->chosen[S] = index;
+    return REXI_OK;
+}
+
+int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
+    std::vector<Schedule>* c = nullptr;
+    int rc = schedules_for(plan, S, &c);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)S * 3 * plan->nspec * 16;
+    void *u0 = nullptr, *u1 = nullptr;
+    REXI_HIP(hipMalloc(&u0, bytes));
+    hipError_t e = hipMalloc(&u1, bytes);
+    if (e != hipSuccess) { (void)hipFree(u0); return hip_fail(e, "hipMalloc"); }
+    hipEvent_t a = nullptr, b = nullptr;
+    int best = -1;
+    float best_ms = 0;
+    rc = REXI_OK;
+    do {
+        if ((e = hipMemsetAsync(u0, 0, bytes, s)) != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync"); break; }
+        if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+            rc = hip_fail(e, "hipEventCreate");
+            break;
+        }
+        for (int i = 0; i < (int)c->size() && !rc; ++i) {
+            const Schedule& sc = (*c)[i];
+            rc = run_steps(plan, sc, u0, u1, S, 1, 0, s);
+            if (rc) break;
+            if ((e = hipEventRecord(a, s)) != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+            rc = run_steps(plan, sc, u0, u1, S, 3, 0, s);
+            if (rc) break;
+            if ((e = hipEventRecord(b, s)) != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+            if ((e = hipEventSynchronize(b)) != hipSuccess) { rc = hip_fail(e, "hipEventSynchronize"); break; }
+            float ms = 0;
+            if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) { rc = hip_fail(e, "hipEventElapsedTime"); break; }
+            if (best < 0 || ms < best_ms) { best = i; best_ms = ms; }
+        }
+    } while (0);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(u0);
+    (void)hipFree(u1);
+    if (rc) return rc;
+    plan->chosen[S] = best;
+    if (chosen) *chosen = best;
+    return REXI_OK;
+}
+
+int sh_forward(rexi_plan* plan, const double* grid, void* spec, int B, void* stream) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    return sh_run(plan, grid, spec, B, true, (hipStream_t)stream);
+}
+
+int sh_inverse(rexi_plan* plan, const void* spec, double* grid, int B, void* stream) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    return sh_run(plan, spec, grid, B, false, (hipStream_t)stream);
+}
+
+}  // extern "C"
