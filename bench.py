@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the T-REXI hot path on one MI355X.
+
+One "step" of this benchmark is the whole job of the T256 workload on one
+batch of synthetic input, already resident in HBM:
+  SH analysis of 4 states x (Phi, vort, div) from a 512x256 Gaussian grid,
+  16 forward T-REXI steps (dt = 10800 s, M = 1024 -> 2071 poles) kept as
+  segments of 4 (checkpoints at segment boundaries),
+  the gradient of ||Phi(T) - Phi_target||^2,
+  16 adjoint steps, and SH synthesis of the resulting gradient.
+The metric is (pole, m)-block solves per second over the timed region:
+2 x 16 x 2071 x 257 blocks per step.
+
+Also reported: live HIP-event timing of the fused solve kernel (roofline
+against the FP64 vector peak), the FP64-MFMA Legendre kernels, the plain
+per-term launch form for comparison, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK = 78.6     # TFLOP/s, MI355X (256 CUs x 2.4 GHz x 128 FP64 flop/clk)
+FP64_MFMA_PEAK = 78.6       # TFLOP/s, MI355X dense FP64 matrix
+HBM_PEAK = 8000.0           # GB/s
+
+
+def solve_flops_per_launch(N, T, S):
+    """Algorithmic FP64 flops of one REXI step of S states (Thomas count).
+
+    Per pole and per (n, m) with (n, m) != (0, 0), both parity chains hold one
+    element each: factorisation 2 x 16 flops (diagonal, pivot update, complex
+    reciprocal, multiplier) and, per right-hand side (2 per state), 2 x 34
+    flops (Phi elimination, forward sweep, back substitution, weighted
+    accumulation of the chain variable and of Phi)."""
+    nspec = (T + 1) * (T + 2) // 2
+    return float(N) * (nspec - 1) * (32 + 136 * S)
+
+
+def legendre_flops(T, nlat, fields):
+    """Algorithmic flops of one Legendre contraction (either direction), using
+    the equatorial symmetry: 2 x (nlat/2) x (2 fields) per coefficient."""
+    nspec = (T + 1) * (T + 2) // 2
+    return 2.0 * (nlat // 2) * (2 * fields) * nspec
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1812_03431_amd", "csrc", "rexi_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(digest):
+    """HBM bytes per solve launch from the committed counter summary, if it was
+    taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "k_solve_t256_fwd_adj_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != digest:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle, as is, on a bounded sample of the workload's orders."""
+    import numpy as np
+    import synth
+    from oracle import coeffs, rexi as orexi
+    A, OM, PB = synth.EARTH_RADIUS, synth.EARTH_OMEGA, synth.GRAVITY * synth.MEAN_DEPTH
+    co = coeffs.rexi_coefficients(w.M, w.h, w.L)
+    N = len(co["alpha"])
+    u0 = synth.random_state(w.T, w.states, 0)
+    stride = 16
+    orders = list(range(0, w.T + 1, stride))
+    t0, c0 = time.perf_counter(), time.process_time()
+    done = []
+    for m in orders:
+        orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, orders=[m])
+        orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, orders=[m], adjoint=True)
+        done.append(m)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    blocks = 2 * N * len(done)
+    return {"value": blocks / wall, "unit": "blocks/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
+            "sample": f"one forward and one adjoint step of {w.states} states for orders m = "
+                      f"{done[0]}..{done[-1]} step {stride} ({len(done)} of {w.T + 1} orders, mean chain "
+                      f"length {np.mean([w.T + 1 - m for m in done]):.0f}); {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="t256_fwd_adj")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 1 GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
+              f"MI355X; the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1812_03431_amd as rexi
+
+    w = synth.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    S = w.states
+    B = 3 * S
+    plan = rexi.plan_for(w, max_states=S, max_fields=B)
+    N, T = plan.n_poles, w.T
+    ck = w.checkpoint_every or w.steps
+    nseg = w.steps // ck
+
+    grid = torch.from_numpy(synth.random_grid(w.nlat, w.nlon, B, 0)).to(dev)
+    target = torch.from_numpy(synth.random_state(T, S, 100)[:, 0].copy()).to(dev)
+    if not args.no_autotune:
+        plan.autotune(S)
+    torch.cuda.synchronize()
+
+    def job():
+        u = plan.sh_forward(grid).view(S, 3, plan.nspec)
+        boundaries = [u]
+        for _ in range(nseg):
+            u = plan.step(u, ck)
+            boundaries.append(u)
+        g = torch.zeros_like(u)
+        g[:, 0] = 2.0 * (u[:, 0] - target)
+        for _ in range(nseg):
+            g = plan.step_adjoint(g, ck)
+        return plan.sh_inverse(g.view(B, plan.nspec))
+
+    for _ in range(args.warmup):
+        job()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = job()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_timing(False)
+    solve_ms, solve_n = plan.kernel_time(plan.KERNEL_SOLVE)
+    lf_ms, lf_n = plan.kernel_time(plan.KERNEL_LEGENDRE_FWD)
+    li_ms, li_n = plan.kernel_time(plan.KERNEL_LEGENDRE_INV)
+    assert torch.isfinite(out).all()
+
+    elapsed = t1 - t0
+    blocks_per_job = 2 * w.steps * N * (T + 1)
+    value = blocks_per_job * args.steps / elapsed
+
+    # the plain per-term launch form vs the batched form, one forward step each
+    u = plan.sh_forward(grid).view(S, 3, plan.nspec)
+    plan.step(u, 1)
+    plan.step_per_term(u)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    plan.step(u, 1)
+    e[1].record()
+    e[2].record()
+    plan.step_per_term(u)
+    e[3].record()
+    torch.cuda.synchronize()
+    batched_ms, per_term_ms = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])
+
+    avg_solve_s = solve_ms / 1e3 / max(1, solve_n)
+    fl = solve_flops_per_launch(N, T, S)
+    achieved = fl / avg_solve_s / 1e12
+    digest = kernel_source_digest()
+    traffic = load_traffic(digest)
+    lflops = legendre_flops(T, w.nlat, B)
+    leg = {}
+    if lf_n and li_n:
+        a_f = lflops / (lf_ms / 1e3 / lf_n) / 1e12
+        a_i = lflops / (li_ms / 1e3 / li_n) / 1e12
+        leg = {"bound": "mfma", "unit": "TFLOP/s", "peak": FP64_MFMA_PEAK,
+               "forward_achieved": round(a_f, 3), "forward_frac": round(a_f / FP64_MFMA_PEAK, 4),
+               "inverse_achieved": round(a_i, 3), "inverse_frac": round(a_i / FP64_MFMA_PEAK, 4),
+               "forward_avg_ms": round(lf_ms / lf_n, 4), "inverse_avg_ms": round(li_ms / li_n, 4),
+               "flops_per_launch": lflops}
+
+    rec = {
+        "metric": "REXI (term,m)-block solves/s and step time fwd+adjoint at T256, <=1e-10 rel L2",
+        "value": value,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded random Gaussian-grid fields (SH analysis input) and a seeded random "
+                "spectral Phi target",
+        "config": {"workload": w.name, "T": T, "grid": f"{w.nlon}x{w.nlat}", "dt_s": w.dt, "M": w.M,
+                   "h": w.h, "poles": N, "states": S, "forward_steps": w.steps, "adjoint_steps": w.steps,
+                   "checkpoint_every": ck, "sh_fields": B, "blocks_per_step": blocks_per_job},
+        "rexi_step_ms": avg_solve_s * 1e3,
+        "fwd_plus_adjoint_step_ms": 2 * avg_solve_s * 1e3,
+        "batched_step_ms": batched_ms,
+        "per_term_step_ms": per_term_ms,
+        "batched_vs_per_term": per_term_ms / batched_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK, "traffic": traffic, "kernel": "k_solve",
+                     "flops_per_launch": fl, "avg_launch_ms": avg_solve_s * 1e3, "launches": solve_n,
+                     "kernel_source_sha256_16": digest},
+        "legendre": leg,
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = 1 << 30
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

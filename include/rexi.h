@@ -167,6 +167,17 @@ int rexi_plan_autotune(rexi_plan *plan, int S, void *stream, int *chosen);
  * number of candidates. */
 int rexi_plan_set_schedule(rexi_plan *plan, int S, int index, int *count);
 
+/* Kernel timing for measurement.  rexi_plan_set_timing(plan, 1) makes the plan
+ * bracket every later launch of the timed kernels with a HIP event pair on the
+ * launch stream; 0 stops recording.  rexi_plan_kernel_time synchronises on the
+ * recorded events and returns the summed elapsed time (ms) and the number of
+ * launches of one kernel since the last query, then forgets them.
+ *   kernel  REXI_KERNEL_SOLVE (fused banded solve), REXI_KERNEL_LEGENDRE_FWD,
+ *           REXI_KERNEL_LEGENDRE_INV */
+enum { REXI_KERNEL_SOLVE = 0, REXI_KERNEL_LEGENDRE_FWD = 1, REXI_KERNEL_LEGENDRE_INV = 2 };
+int rexi_plan_set_timing(rexi_plan *plan, int enable);
+int rexi_plan_kernel_time(rexi_plan *plan, int kernel, double *total_ms, long long *launches);
+
 /* Description of the last non-zero return on this thread ("" if none). */
 const char *rexi_last_error(void);
 

@@ -77,7 +77,7 @@ struct Group {
 };
 
 struct Schedule {
-    int SM = 4;       // elements per lane (template)
+    int SM = 4;       // elements per lane (template, even)
     int ST = 1;       // states per wave (template)
     int S = 0;        // states this schedule serves
     std::vector<MInfo> minfo;
@@ -105,10 +105,9 @@ struct rexi_plan {
     // per-(n, m) constants in spectral order (device)
     double *d_th = nullptr, *d_om = nullptr, *d_cc = nullptr, *d_sc = nullptr;
     int *d_idx_n = nullptr, *d_idx_m = nullptr;
-    // poles for forward and adjoint weights (device, double2)
-    double2 *d_alpha = nullptr, *d_ainv = nullptr;
-    double2 *d_wx[2] = {nullptr, nullptr}, *d_wy[2] = {nullptr, nullptr};
-    double2 *d_wxa[2] = {nullptr, nullptr}, *d_wya[2] = {nullptr, nullptr};
+    // per pole, forward [0] and adjoint [1]: alpha, 1/alpha, wx, wy, wx/alpha,
+    // wy/alpha (6 complex, see rexi_kernels.hip)
+    double2* d_poles[2] = {nullptr, nullptr};
     // workspace (sized for max_states)
     double2 *d_ch_var[2] = {nullptr, nullptr};  // [S][nslots + 2]
     double2 *d_ch_phi[2] = {nullptr, nullptr};  // [S][nspec]
@@ -134,4 +133,14 @@ struct rexi_plan {
     void* d_tiles_f = nullptr;    // Legendre tiles, forward / inverse
     void* d_tiles_i = nullptr;
     int ntiles_f = 0, ntiles_i = 0;
+
+    // measurement: event pairs around timed launches, per kernel kind
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[3];
 };
+
+namespace rexi {
+// Record an event before / after a timed launch when timing is on.
+hipError_t timed_begin(rexi_plan* pl, int kind, hipStream_t s);
+hipError_t timed_end(rexi_plan* pl, int kind, hipStream_t s);
+}  // namespace rexi

@@ -16,6 +16,7 @@
 namespace rexi {
 
 bool solve_variant_supported(int SM, int ST);
+int solve_waves_per_item();
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
                         hipStream_t s);
 hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int adjoint, hipStream_t s);
@@ -38,6 +39,22 @@ int fail(int code, const std::string& msg) {
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(REXI_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hipError_t timed_begin(rexi_plan* pl, int kind, hipStream_t s) {
+    if (!pl->timing) return hipSuccess;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) { (void)hipEventDestroy(a); return e; }
+    pl->events[kind].push_back({a, b});
+    return hipEventRecord(a, s);
+}
+
+hipError_t timed_end(rexi_plan* pl, int kind, hipStream_t s) {
+    if (!pl->timing || pl->events[kind].empty()) return hipSuccess;
+    return hipEventRecord(pl->events[kind].back().second, s);
 }
 
 namespace {
@@ -128,14 +145,12 @@ int build_schedule(rexi_plan* pl, int S, int SM, int ST, long long target_items,
         int P = 1;
         while (P * SM < mi.L) P *= 2;
         if (P > 64) return fail(REXI_EUNSUPPORTED, "chain too long for this tiling");
-        int s = (mi.L + P - 1) / P;
-        if (s < 2) s = 2;
         mi.P = P;
-        mi.s = s;
-        const int G = 64 / P;
+        mi.s = SM;
+        const int G = 64 / P * solve_waves_per_item();  // poles per workgroup iteration
         int lg = 0;
         while ((1 << lg) < P) ++lg;
-        const double it_cost = s * (36.0 + 2 * ST * 40.0) + lg * (36.0 + 2 * ST * 8.0) + 20.0;
+        const double it_cost = SM * (30.0 + 2 * ST * 30.0) + lg * (40.0 + 2 * ST * 10.0) + 30.0;
         const int iters = (N + G - 1) / G;
         for (int p = 0; p < 2; ++p)
             for (int t = 0; t < ntiles; ++t) {
@@ -205,9 +220,9 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
     }
     std::vector<Schedule>& c = pl->sched[S];
     if (c.empty()) {
-        const int sms[] = {4, 8};
-        const int sts[] = {1, 2, 4};
-        const long long tg[] = {2048, 8192, 32768};
+        const int sms[] = {4, 6, 8, 10, 12, 16};
+        const int sts[] = {1};
+        const long long tg[] = {1024, 2048, 4096};
         for (int SM : sms)
             for (int ST : sts) {
                 if (!solve_variant_supported(SM, ST)) continue;
@@ -223,14 +238,13 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
                 }
             }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
-        // default: SM 4, the largest state tile that divides the work, 8192 items
+        // default until autotuned: 8 elements per lane, ~2048 work items
         int best = 0;
         for (int i = 0; i < (int)c.size(); ++i) {
             const Schedule& s = c[i];
-            const int want_st = S >= 2 ? 2 : 1;
-            if (s.SM == 4 && s.ST == want_st && s.name.find("items") != std::string::npos) {
+            if (s.SM == 8) {
                 best = i;
-                if (s.items.size() >= 4096) break;
+                if (s.items.size() >= 2048) break;
             }
         }
         pl->chosen[S] = best;
@@ -267,7 +281,9 @@ int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S
     int cur = 0;
     for (int k = 0; k < nsteps; ++k) {
         const bool last = (k == nsteps - 1);
+        REXI_HIP(timed_begin(pl, REXI_KERNEL_SOLVE, s));
         REXI_HIP(enqueue_solve(pl, sc, cur, S, adjoint, s));
+        REXI_HIP(timed_end(pl, REXI_KERNEL_SOLVE, s));
         REXI_HIP(enqueue_reduce(pl, sc, pl->d_part, cur, cur ^ 1, last ? u1 : nullptr, S, adjoint, pl->d_slot_m, s));
         cur ^= 1;
     }
@@ -290,7 +306,18 @@ int do_step(rexi_plan* pl, const void* u0, void* u1, int S, int nsteps, int adjo
     return run_steps(pl, (*c)[pl->chosen[S]], u0, u1, S, nsteps, adjoint, (hipStream_t)stream);
 }
 
+void drop_events(rexi_plan* pl) {
+    for (auto& v : pl->events) {
+        for (auto& ab : v) {
+            (void)hipEventDestroy(ab.first);
+            (void)hipEventDestroy(ab.second);
+        }
+        v.clear();
+    }
+}
+
 void release(rexi_plan* pl) {
+    drop_events(pl);
     for (auto& c : pl->sched)
         for (auto& s : c) free_schedule(s);
     for (auto& s : pl->per_term) free_schedule(s);
@@ -300,13 +327,8 @@ void release(rexi_plan* pl) {
     dev_free(pl->d_sc);
     dev_free(pl->d_idx_n);
     dev_free(pl->d_idx_m);
-    dev_free(pl->d_alpha);
-    dev_free(pl->d_ainv);
     for (int d = 0; d < 2; ++d) {
-        dev_free(pl->d_wx[d]);
-        dev_free(pl->d_wy[d]);
-        dev_free(pl->d_wxa[d]);
-        dev_free(pl->d_wya[d]);
+        dev_free(pl->d_poles[d]);
         dev_free(pl->d_ch_var[d]);
         dev_free(pl->d_ch_phi[d]);
     }
@@ -400,13 +422,18 @@ int create(const rexi_params* p, rexi_plan** out) {
     if (!rc) rc = upload(&pl->d_sc, sc);
     if (!rc) rc = upload(&pl->d_idx_n, in);
     if (!rc) rc = upload(&pl->d_idx_m, im);
-    if (!rc) rc = upload(&pl->d_alpha, to_d2(pl->poles.alpha));
-    if (!rc) rc = upload(&pl->d_ainv, to_d2(ainv));
     for (int d = 0; d < 2 && !rc; ++d) {
-        rc = upload(&pl->d_wx[d], to_d2(wx[d]));
-        if (!rc) rc = upload(&pl->d_wy[d], to_d2(wy[d]));
-        if (!rc) rc = upload(&pl->d_wxa[d], to_d2(wxa[d]));
-        if (!rc) rc = upload(&pl->d_wya[d], to_d2(wya[d]));
+        std::vector<std::complex<double>> pd;
+        pd.reserve(6 * (size_t)N);
+        for (int k = 0; k < N; ++k) {
+            pd.push_back(pl->poles.alpha[k]);
+            pd.push_back(ainv[k]);
+            pd.push_back(wx[d][k]);
+            pd.push_back(wy[d][k]);
+            pd.push_back(wxa[d][k]);
+            pd.push_back(wya[d][k]);
+        }
+        rc = upload(&pl->d_poles[d], to_d2(pd));
     }
     if (!rc) rc = upload(&pl->sched_layout, lay);
     if (!rc) rc = upload(&pl->d_slot_m, slot_m);
@@ -597,6 +624,32 @@ int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
     if (rc) return rc;
     plan->chosen[S] = best;
     if (chosen) *chosen = best;
+    return REXI_OK;
+}
+
+int rexi_plan_set_timing(rexi_plan* plan, int enable) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    plan->timing = enable != 0;
+    return REXI_OK;
+}
+
+int rexi_plan_kernel_time(rexi_plan* plan, int kernel, double* total_ms, long long* launches) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (kernel < 0 || kernel > 2) return fail(REXI_EINVAL, "unknown kernel");
+    double tot = 0;
+    long long n = 0;
+    for (auto& ab : plan->events[kernel]) {
+        REXI_HIP(hipEventSynchronize(ab.second));
+        float ms = 0;
+        REXI_HIP(hipEventElapsedTime(&ms, ab.first, ab.second));
+        tot += ms;
+        ++n;
+        (void)hipEventDestroy(ab.first);
+        (void)hipEventDestroy(ab.second);
+    }
+    plan->events[kernel].clear();
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = n;
     return REXI_OK;
 }
 

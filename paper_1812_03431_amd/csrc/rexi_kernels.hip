@@ -84,18 +84,18 @@ __device__ __forceinline__ cd crcp(cd a) {
 }
 __device__ __forceinline__ cd shfl(cd v, int src) { return cd{__shfl(v.r, src, 64), __shfl(v.i, src, 64)}; }
 
+// Per-pole data: pole, its reciprocal and the four weights (see top).
+struct __align__(16) PoleData {
+    double2 al, ai, wx, wy, wxa, wya;
+};
+
 struct SolveArgs {
     const Item* items;
     const MInfo* minfo;
     const double* th;   // dt theta_{n,m}
     const double* om;   // dt w_n
     const double* cc;   // 2 Omega dt kappa_{n,m}: coupling of degrees n-1 and n
-    const double2* alpha;
-    const double2* ainv;
-    const double2* wx;
-    const double2* wy;
-    const double2* wxa;
-    const double2* wya;
+    const PoleData* poles;
     const double2* ch_var;  // [S][nslots + 2]
     const double2* ch_phi;  // [S][nspec]
     double2* part;
@@ -103,240 +103,251 @@ struct SolveArgs {
     long long var_stride, nspec;
 };
 
-// ACCUM = true: add into part (per-term form, one launch per pole) instead of storing.
-template <int SM, int ST, bool ACCUM>
-__global__ void __launch_bounds__(64) k_solve(const SolveArgs A) {
-    const Item it = A.items[blockIdx.x];
-    const MInfo mi = A.minfo[it.m];
-    const int lane = threadIdx.x;
-    const int P = mi.P, s = mi.s, L = mi.L, n0 = mi.n0, p = it.p, m = it.m;
-    const int G = 64 / P;
-    const int g = lane / P;
-    const int l = lane - g * P;
-    const int S0 = it.tile * ST;
-    const int nst = min(ST, A.S - S0);
+constexpr int kWaves = 4;  // waves per workgroup; they share one item's staged data
 
-    // ---- per-element constants and (pole-independent) right-hand sides
-    double th[SM], om[SM], ca[SM], cb[SM], jv[SM];
-    bool dl[SM], vd[SM];
-    cd rv[ST][SM], rp[ST][SM];
-#pragma unroll
-    for (int t = 0; t < SM; ++t) {
-        const int j = l * s + t;
+__device__ __forceinline__ cd crcp_newton(cd a) {
+    // 1/(x + i y) = (x - i y)/(x^2 + y^2); the real reciprocal by v_rcp_f64 and
+    // two Newton-Raphson steps r <- r + r (1 - d r).
+    const double d = fma(a.r, a.r, a.i * a.i);
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return cd{a.r * r, -a.i * r};
+}
+
+// One work item: chain p of order m, one state, a pole range.  SE elements per
+// lane (even, compile time); PH fixes the element types: element t of every
+// lane is a divergence element iff (t + PH) is odd.
+//
+// Per pole each lane runs one forward sweep over its interior elements
+// t = 0..SE-2 that at once forms the pivots q, multipliers e = q c, the
+// forward part gv of the left spike and the forward parts G of both
+// right-hand sides, and accumulates, with the running product
+// pi_t = prod_{s<t} (-e_s), the back-substituted first elements
+// (y_0 = sum_t pi_t Y_t) that the left neighbour's interface row needs.  The
+// interface rows (one per lane) are solved by cyclic reduction across the
+// chain's P lanes, matrix and both right-hand sides in the same steps, and a
+// reverse sweep recovers the interior with both interface values.
+template <int SE, int PH, bool ACCUM>
+__device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, const MInfo& mi, double* sm) {
+    constexpr int NI = SE - 1;  // interior elements 0 .. SE-2; interface SE-1
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int P = mi.P, L = mi.L, n0 = mi.n0, m = it.m, p = it.p;
+    const int G = 64 / P;
+    const int g = lane / P, l = lane - g * P;
+    const int st = it.tile;
+    const int npos = P * SE;
+
+    // ---- stage the item's constants and right-hand side in LDS, [t][l] order:
+    // per position (th, om, cl, cr, rv.r, rv.i, rp.r, rp.i)
+    double* c = sm;
+    for (int j = tid; j < npos; j += blockDim.x) {
+        const int l2 = j / SE, t2 = j - l2 * SE;
         const int n = n0 + j;
-        vd[t] = (t < s) && (j < L);
-        th[t] = om[t] = ca[t] = cb[t] = 0.0;
-        jv[t] = 1.0;
-        dl[t] = false;
-#pragma unroll
-        for (int q = 0; q < ST; ++q) rv[q][t] = rp[q][t] = mk(0, 0);
-        if (vd[t]) {
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (j < L) {
             const long long i = mi.spec_off + (n - m);
-            th[t] = A.th[i];
-            om[t] = A.om[i];
-            dl[t] = ((n + p) & 1) != 0;
-            const double sg = dl[t] ? 1.0 : -1.0;
-            ca[t] = (j > 0) ? sg * A.cc[i] : 0.0;
-            cb[t] = (n < A.T) ? sg * A.cc[i + 1] : 0.0;
-            jv[t] = (n & 1) ? 1.0 : -1.0;
-            const long long slot = mi.slot_base + (long long)p * L + j;
-#pragma unroll
-            for (int q = 0; q < ST; ++q) {
-                if (q < nst) {
-                    rv[q][t] = ld2(A.ch_var, (S0 + q) * A.var_stride + slot);
-                    if (dl[t]) rp[q][t] = ld2(A.ch_phi, (S0 + q) * A.nspec + i);
-                }
+            v[0] = A.th[i];
+            v[1] = A.om[i];
+            v[2] = (j > 0) ? A.cc[i] : 0.0;
+            v[3] = (n < A.T) ? A.cc[i + 1] : 0.0;
+            const double2 rv = A.ch_var[st * A.var_stride + mi.slot_base + (long long)p * L + j];
+            v[4] = rv.x;
+            v[5] = rv.y;
+            if ((n + p) & 1) {
+                const double2 rp = A.ch_phi[st * A.nspec + i];
+                v[6] = rp.x;
+                v[7] = rp.y;
             }
         }
+        double* o = c + (size_t)(t2 * P + l2) * 8;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) o[r] = v[r];
     }
+    __syncthreads();
 
-    cd av[ST][SM], ap[ST][SM];
+    bool vd[SE];
 #pragma unroll
-    for (int q = 0; q < ST; ++q)
+    for (int t = 0; t < SE; ++t) vd[t] = (l * SE + t) < L;
+    const double jb = (n0 & 1) ? 1.0 : -1.0;  // J sign of the chain variable at even t
+
+    cd av[SE], ap[SE];
 #pragma unroll
-        for (int t = 0; t < SM; ++t) av[q][t] = ap[q][t] = mk(0, 0);
+    for (int t = 0; t < SE; ++t) av[t] = ap[t] = mk(0, 0);
 
     const int src_dn = (lane + 1) & 63;
     const int src_up = (lane + 63) & 63;
+    const bool lastl = (l == P - 1), firstl = (l == 0);
+    const int stride = kWaves * G;
 
-    for (int kb = it.k0; kb < it.k1; kb += G) {
-        const int k = kb + g;
+    for (int kb = it.k0; kb < it.k1; kb += stride) {
+        if (kb + wave * G >= it.k1) continue;  // this wave has no pole left (uniform)
+        const int k = kb + wave * G + g;
         const bool act = k < it.k1;
-        const int kk = act ? k : kb;
-        const cd al = ld2(A.alpha, kk), ai = ld2(A.ainv, kk);
-        const cd wx = act ? ld2(A.wx, kk) : mk(0, 0);
-        const cd wy = act ? ld2(A.wy, kk) : mk(0, 0);
-        const cd wxa = act ? ld2(A.wxa, kk) : mk(0, 0);
-        const cd wya = act ? ld2(A.wya, kk) : mk(0, 0);
+        const PoleData& pd = A.poles[act ? k : it.k0];
+        const cd al = cd{pd.al.x, pd.al.y}, ai = cd{pd.ai.x, pd.ai.y};
 
-        // diagonal b and Phi-elimination factor f = dt w_n / alpha
-        cd b[SM], f[SM];
-#pragma unroll
-        for (int t = 0; t < SM; ++t) {
-            f[t] = mk(0, 0);
-            b[t] = mk(1, 0);
-            if (vd[t]) {
-                if (dl[t]) f[t] = cscale(ai, om[t]);
-                b[t] = mk(al.r + om[t] * f[t].r, al.i + th[t] + om[t] * f[t].i);
+        cd e[NI], gv[NI], Gu[NI], Gw[NI];
+        cd pi = mk(1, 0), v0 = mk(0, 0), w0 = mk(0, 0), g0u = mk(0, 0), g0w = mk(0, 0);
+        cd qprev = mk(0, 0);
+        double cbprev = 0.0;
+        // element data of position t of this lane: diagonal b, couplings, RHS
+        auto element = [&](int t, cd& b, double& ca, double& cb, cd& du, cd& dw) {
+            const double* o = c + (size_t)(t * P + l) * 8;
+            const double sg = ((PH + t) & 1) ? 1.0 : -1.0;
+            ca = sg * o[2];
+            cb = sg * o[3];
+            const cd rv = cd{o[4], o[5]};
+            const double jv = (t & 1) ? -jb : jb;
+            if ((PH + t) & 1) {
+                const double om = o[1];
+                const cd f = cscale(ai, om);
+                b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, o[0]));
+                const cd rp = cd{o[6], o[7]};
+                du = cfms(rv, f, rp);
+                dw = cscale(cadd(cconj(rv), cmul(f, cconj(rp))), jv);
+            } else {
+                b = mk(al.r, al.i + o[0]);
+                du = rv;
+                dw = cscale(cconj(rv), jv);
             }
-        }
-
-        // interior factorisation (t = 0 .. s-2) and spikes v (left), w (right)
-        cd q[SM], e[SM], v[SM], w[SM];
+        };
 #pragma unroll
-        for (int t = 0; t < SM; ++t) q[t] = e[t] = v[t] = w[t] = mk(0, 0);
-#pragma unroll
-        for (int t = 0; t < SM - 1; ++t) {
-            if (t < s - 1) {
-                cd bp = b[t];
-                if (t > 0) bp = csubs(bp, ca[t] * cb[t - 1], q[t - 1]);
-                q[t] = crcp(bp);
-                e[t] = cscale(q[t], cb[t]);
-                v[t] = (t == 0) ? cscale(q[0], ca[0]) : cmul(q[t], cscale(v[t - 1], -ca[t]));
+        for (int t = 0; t < NI; ++t) {
+            cd b, du, dw;
+            double ca, cb;
+            element(t, b, ca, cb, du, dw);
+            if (t > 0) b = csubs(b, ca * cbprev, qprev);
+            const cd q = crcp_newton(b);
+            e[t] = cscale(q, cb);
+            if (t == 0) {
+                gv[0] = cscale(q, ca);
+                Gu[0] = cmul(q, du);
+                Gw[0] = cmul(q, dw);
+            } else {
+                gv[t] = cmul(q, cscale(gv[t - 1], -ca));
+                Gu[t] = cmul(q, csubs(du, ca, Gu[t - 1]));
+                Gw[t] = cmul(q, csubs(dw, ca, Gw[t - 1]));
             }
-        }
-#pragma unroll
-        for (int t = SM - 3; t >= 0; --t)
-            if (t < s - 2) v[t] = cfms(v[t], e[t], v[t + 1]);
-#pragma unroll
-        for (int t = SM - 2; t >= 0; --t) {
-            if (t == s - 2) w[t] = e[t];
-            else if (t < s - 2) w[t] = cneg(cmul(e[t], w[t + 1]));
+            v0 = cfma(v0, pi, gv[t]);
+            g0u = cfma(g0u, pi, Gu[t]);
+            g0w = cfma(g0w, pi, Gw[t]);
+            if (t == NI - 1) w0 = cmul(pi, e[t]);
+            pi = cneg(cmul(pi, e[t]));
+            qprev = q;
+            cbprev = cb;
         }
 
-        // interface row (t = s-1) reduced to the lanes' interface unknowns X
-        double aI = 0.0, cI = 0.0;
-        cd bI = mk(1, 0), vL = mk(0, 0), wL = mk(0, 0);
-#pragma unroll
-        for (int t = 0; t < SM; ++t)
-            if (t == s - 1) { aI = ca[t]; cI = cb[t]; bI = b[t]; }
-#pragma unroll
-        for (int t = 0; t < SM - 1; ++t)
-            if (t == s - 2) { vL = v[t]; wL = w[t]; }
-        const bool last = (l == P - 1);
-        const bool first = (l == 0);
-        cd vN = shfl(v[0], src_dn), wN = shfl(w[0], src_dn);
-        if (last) vN = wN = mk(0, 0);
-        cd Ac = cneg(cscale(vL, aI));
-        cd Bc = csubs(csubs(bI, aI, wL), cI, vN);
+        // interface row -> tridiagonal system over the P lanes of the chain
+        cd bI, dIu, dIw;
+        double aI, cI;
+        element(SE - 1, bI, aI, cI, dIu, dIw);
+        cd vN = shfl(v0, src_dn), wN = shfl(w0, src_dn);
+        cd guN = shfl(g0u, src_dn), gwN = shfl(g0w, src_dn);
+        if (lastl) vN = wN = guN = gwN = mk(0, 0);
+        cd Ac = cneg(cscale(gv[NI - 1], aI));
+        cd Bc = csubs(csubs(bI, aI, e[NI - 1]), cI, vN);
         cd Cc = cneg(cscale(wN, cI));
+        cd Du = csubs(csubs(dIu, aI, Gu[NI - 1]), cI, guN);
+        cd Dw = csubs(csubs(dIw, aI, Gw[NI - 1]), cI, gwN);
 
-        // right-hand sides: r = 2 q + kind, kind 0: u, kind 1: conj(J u)
-        cd x[2 * ST][SM];
-        cd D[2 * ST];
-#pragma unroll
-        for (int r = 0; r < 2 * ST; ++r) {
-            const int qs = r >> 1;
-#pragma unroll
-            for (int t = 0; t < SM; ++t) {
-                if (r & 1) {
-                    const cd z = cadd(cconj(rv[qs][t]), cmul(f[t], cconj(rp[qs][t])));
-                    x[r][t] = cscale(z, jv[t]);
-                } else {
-                    x[r][t] = cfms(rv[qs][t], f[t], rp[qs][t]);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < SM - 1; ++t) {
-                if (t < s - 1) {
-                    const cd y = (t == 0) ? x[r][0] : csubs(x[r][t], ca[t], x[r][t - 1]);
-                    x[r][t] = cmul(q[t], y);
-                }
-            }
-#pragma unroll
-            for (int t = SM - 3; t >= 0; --t)
-                if (t < s - 2) x[r][t] = cfms(x[r][t], e[t], x[r][t + 1]);
-            cd dI = mk(0, 0), gL = mk(0, 0);
-#pragma unroll
-            for (int t = 0; t < SM; ++t)
-                if (t == s - 1) dI = x[r][t];
-#pragma unroll
-            for (int t = 0; t < SM - 1; ++t)
-                if (t == s - 2) gL = x[r][t];
-            cd gN = shfl(x[r][0], src_dn);
-            if (last) gN = mk(0, 0);
-            D[r] = csubs(csubs(dI, aI, gL), cI, gN);
-        }
-
-        // parallel cyclic reduction over the P interface unknowns of a chain
+        // cyclic reduction: matrix and both right-hand sides together
         for (int d = 1; d < P; d <<= 1) {
-            const cd ib = crcp(Bc);
+            const cd ib = crcp_newton(Bc);
             const int sl = (lane - d) & 63, sr = (lane + d) & 63;
             const bool hl = l >= d, hr = l + d < P;
-            cd AL = shfl(Ac, sl), CL = shfl(Cc, sl), IL = shfl(ib, sl);
-            cd AR = shfl(Ac, sr), CR = shfl(Cc, sr), IR = shfl(ib, sr);
-            if (!hl) AL = CL = IL = mk(0, 0);
-            if (!hr) AR = CR = IR = mk(0, 0);
+            cd AL = shfl(Ac, sl), CL = shfl(Cc, sl), IL = shfl(ib, sl), DuL = shfl(Du, sl), DwL = shfl(Dw, sl);
+            cd AR = shfl(Ac, sr), CR = shfl(Cc, sr), IR = shfl(ib, sr), DuR = shfl(Du, sr), DwR = shfl(Dw, sr);
+            if (!hl) AL = CL = IL = DuL = DwL = mk(0, 0);
+            if (!hr) AR = CR = IR = DuR = DwR = mk(0, 0);
             const cd k1 = cmul(Ac, IL), k2 = cmul(Cc, IR);
-#pragma unroll
-            for (int r = 0; r < 2 * ST; ++r) {
-                cd DL = shfl(D[r], sl), DR = shfl(D[r], sr);
-                if (!hl) DL = mk(0, 0);
-                if (!hr) DR = mk(0, 0);
-                D[r] = cfms(cfms(D[r], k1, DL), k2, DR);
-            }
             Bc = cfms(cfms(Bc, k1, CL), k2, AR);
+            Du = cfms(cfms(Du, k1, DuL), k2, DuR);
+            Dw = cfms(cfms(Dw, k1, DwL), k2, DwR);
             Ac = cneg(cmul(k1, AL));
             Cc = cneg(cmul(k2, CR));
         }
-        const cd iB = crcp(Bc);
+        const cd iB = crcp_newton(Bc);
+        const cd Xu = cmul(Du, iB), Xw = cmul(Dw, iB);
+        cd XLu = shfl(Xu, src_up), XLw = shfl(Xw, src_up);
+        if (firstl) XLu = XLw = mk(0, 0);
 
-        // recovery and beta-weighted accumulation
+        // reverse sweep with both interface values; weighted sums
+        cd wx = cd{pd.wx.x, pd.wx.y}, wy = cd{pd.wy.x, pd.wy.y};
+        cd wxa = cd{pd.wxa.x, pd.wxa.y}, wya = cd{pd.wya.x, pd.wya.y};
+        if (!act) wx = wy = wxa = wya = mk(0, 0);
+        cd xu = Xu, xw = Xw;
 #pragma unroll
-        for (int r = 0; r < 2 * ST; ++r) {
-            const int qs = r >> 1;
-            const cd X = cmul(D[r], iB);
-            cd XL = shfl(X, src_up);
-            if (first) XL = mk(0, 0);
-#pragma unroll
-            for (int t = 0; t < SM; ++t) {
-                if (t < s) {
-                    const cd xv = (t == s - 1) ? X : cfms(cfms(x[r][t], v[t], XL), w[t], X);
-                    if (vd[t]) {
-                        if (r & 1) {
-                            av[qs][t] = cfma_conj(av[qs][t], jv[t], wy, xv);
-                            if (dl[t]) ap[qs][t] = cfma_conj(ap[qs][t], -jv[t], wya, xv);
-                        } else {
-                            av[qs][t] = cfma(av[qs][t], wx, xv);
-                            if (dl[t]) ap[qs][t] = cfma(ap[qs][t], wxa, xv);
-                        }
-                    }
-                }
+        for (int t = SE - 1; t >= 0; --t) {
+            if (t < NI) {
+                xu = cfms(cfms(Gu[t], XLu, gv[t]), e[t], xu);
+                xw = cfms(cfms(Gw[t], XLw, gv[t]), e[t], xw);
+            }
+            if (vd[t]) {
+                const double jv = (t & 1) ? -jb : jb;
+                av[t] = cfma_conj(cfma(av[t], wx, xu), jv, wy, xw);
+                if ((PH + t) & 1) ap[t] = cfma_conj(cfma(ap[t], wxa, xu), -jv, wya, xw);
             }
         }
     }
 
-    // add the G groups' sums (same chain positions) in a fixed tree order
+    // sum the G groups of each wave (same positions) in a fixed tree order
     for (int off = 32; off >= P; off >>= 1) {
         const int src = (lane + off) & 63;
 #pragma unroll
-        for (int qq = 0; qq < ST; ++qq)
-#pragma unroll
-            for (int t = 0; t < SM; ++t) {
-                av[qq][t] = cadd(av[qq][t], shfl(av[qq][t], src));
-                ap[qq][t] = cadd(ap[qq][t], shfl(ap[qq][t], src));
-            }
-    }
-    if (g == 0) {
-#pragma unroll
-        for (int qq = 0; qq < ST; ++qq) {
-            if (qq >= nst) continue;
-#pragma unroll
-            for (int t = 0; t < SM; ++t) {
-                if (!vd[t]) continue;
-                const int j = l * s + t;
-                const long long o0 = it.part_off + ((long long)(qq * 2 + 0) * L + j);
-                const long long o1 = it.part_off + ((long long)(qq * 2 + 1) * L + j);
-                if (ACCUM) {
-                    st2(A.part, o0, cadd(ld2(A.part, o0), av[qq][t]));
-                    st2(A.part, o1, cadd(ld2(A.part, o1), ap[qq][t]));
-                } else {
-                    st2(A.part, o0, av[qq][t]);
-                    st2(A.part, o1, ap[qq][t]);
-                }
-            }
+        for (int t = 0; t < SE; ++t) {
+            av[t] = cadd(av[t], shfl(av[t], src));
+            if ((PH + t) & 1) ap[t] = cadd(ap[t], shfl(ap[t], src));
         }
     }
+    // then the waves, in order, through LDS (reusing the staging area)
+    __syncthreads();
+    double2* acc = reinterpret_cast<double2*>(sm);  // [2][SE][P]
+    for (int wv = 0; wv < kWaves; ++wv) {
+        if (wave == wv && g == 0) {
+#pragma unroll
+            for (int t = 0; t < SE; ++t) {
+                const int o0 = t * P + l, o1 = (SE + t) * P + l;
+                double2 a0 = make_double2(av[t].r, av[t].i);
+                double2 a1 = make_double2(ap[t].r, ap[t].i);
+                if (wv > 0) {
+                    a0.x += acc[o0].x;
+                    a0.y += acc[o0].y;
+                    a1.x += acc[o1].x;
+                    a1.y += acc[o1].y;
+                }
+                acc[o0] = a0;
+                acc[o1] = a1;
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < 2 * L; idx += blockDim.x) {
+        const int plane = idx / L;
+        const int j = idx - plane * L;
+        const int l2 = j / SE, t2 = j - l2 * SE;
+        if (plane == 1 && !(((PH + t2) & 1) != 0)) continue;
+        const double2 v = acc[(plane * SE + t2) * P + l2];
+        const long long o = it.part_off + ((long long)plane * L + j);
+        if (ACCUM) {
+            const double2 old = A.part[o];
+            A.part[o] = make_double2(old.x + v.x, old.y + v.y);
+        } else {
+            A.part[o] = v;
+        }
+    }
+}
+
+template <int SE, bool ACCUM>
+__global__ void __launch_bounds__(256) k_solve(const SolveArgs A) {
+    extern __shared__ double sm[];
+    const Item it = A.items[blockIdx.x];
+    const MInfo mi = A.minfo[it.m];
+    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM>(A, it, mi, sm);
+    else solve_item<SE, 0, ACCUM>(A, it, mi, sm);
 }
 
 // Layout conversion: physical state [S][3][nspec] -> chain layout, scaled.
@@ -445,25 +456,35 @@ __global__ void k_zero(double2* p, long long n) {
     if (gid < n) p[gid] = make_double2(0.0, 0.0);
 }
 
-template <int SM, int ST, bool ACC>
+template <int SE, bool ACC>
 hipError_t launch_solve_t(const SolveArgs& a, int nitems, hipStream_t s) {
-    hipLaunchKernelGGL((k_solve<SM, ST, ACC>), dim3(nitems), dim3(64), 0, s, a);
+    const size_t lds = sizeof(double) * 8 * (size_t)(64 * SE);
+    hipLaunchKernelGGL((k_solve<SE, ACC>), dim3(nitems), dim3(64 * kWaves), lds, s, a);
     return hipGetLastError();
 }
 
 template <bool ACC>
-hipError_t launch_solve(int SM, int ST, const SolveArgs& a, int nitems, hipStream_t s) {
-    if (SM == 4 && ST == 1) return launch_solve_t<4, 1, ACC>(a, nitems, s);
-    if (SM == 4 && ST == 2) return launch_solve_t<4, 2, ACC>(a, nitems, s);
-    if (SM == 8 && ST == 1) return launch_solve_t<8, 1, ACC>(a, nitems, s);
-    return hipErrorInvalidValue;
+hipError_t launch_solve(int SE, int ST, const SolveArgs& a, int nitems, hipStream_t s) {
+    if (ST != 1) return hipErrorInvalidValue;
+    switch (SE) {
+        case 4: return launch_solve_t<4, ACC>(a, nitems, s);
+        case 6: return launch_solve_t<6, ACC>(a, nitems, s);
+        case 8: return launch_solve_t<8, ACC>(a, nitems, s);
+        case 10: return launch_solve_t<10, ACC>(a, nitems, s);
+        case 12: return launch_solve_t<12, ACC>(a, nitems, s);
+        case 16: return launch_solve_t<16, ACC>(a, nitems, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 // Tilings compiled into the library (elements per lane x states per wave).
 // Larger tiles exceed the register file and spill to scratch memory.
-bool solve_variant_supported(int SM, int ST) { return (SM == 4 && (ST == 1 || ST == 2)) || (SM == 8 && ST == 1); }
+bool solve_variant_supported(int SE, int ST) {
+    return ST == 1 && (SE == 4 || SE == 6 || SE == 8 || SE == 10 || SE == 12 || SE == 16);
+}
+int solve_waves_per_item() { return kWaves; }
 
 // Internal launchers used by the C ABI (plan.cpp).
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
@@ -483,12 +504,7 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
     a.th = pl->d_th;
     a.om = pl->d_om;
     a.cc = pl->d_cc;
-    a.alpha = pl->d_alpha;
-    a.ainv = pl->d_ainv;
-    a.wx = pl->d_wx[adjoint];
-    a.wy = pl->d_wy[adjoint];
-    a.wxa = pl->d_wxa[adjoint];
-    a.wya = pl->d_wya[adjoint];
+    a.poles = reinterpret_cast<const PoleData*>(pl->d_poles[adjoint]);
     a.ch_var = pl->d_ch_var[buf];
     a.ch_phi = pl->d_ch_phi[buf];
     a.part = pl->d_part;
@@ -545,12 +561,7 @@ hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int b
     a.th = pl->d_th;
     a.om = pl->d_om;
     a.cc = pl->d_cc;
-    a.alpha = pl->d_alpha + k;
-    a.ainv = pl->d_ainv + k;
-    a.wx = pl->d_wx[0] + k;
-    a.wy = pl->d_wy[0] + k;
-    a.wxa = pl->d_wxa[0] + k;
-    a.wya = pl->d_wya[0] + k;
+    a.poles = reinterpret_cast<const PoleData*>(pl->d_poles[0]) + k;
     a.ch_var = pl->d_ch_var[buf];
     a.ch_phi = pl->d_ch_phi[buf];
     a.part = pl->d_acc;

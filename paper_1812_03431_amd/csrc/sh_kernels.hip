@@ -286,13 +286,17 @@ int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStr
         hipLaunchKernelGGL(k_fft_forward, dim3(B * pl->nlat), dim3(256), lds, s, (const double*)in, pl->d_four,
                            pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);
         REXI_HIP(hipGetLastError());
+        REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_FWD, s));
         hipLaunchKernelGGL(k_legendre_forward, dim3(pl->ntiles_f), dim3(64), 0, s, (const LegTile*)pl->d_tiles_f,
                            pl->d_plm, pl->d_wts, pl->d_four, (double*)out, pl->T, pl->nlat, pl->nhalf, C);
         REXI_HIP(hipGetLastError());
+        REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_FWD, s));
     } else {
+        REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_INV, s));
         hipLaunchKernelGGL(k_legendre_inverse, dim3(pl->ntiles_i), dim3(64), 0, s, (const LegTile*)pl->d_tiles_i,
                            pl->d_plm, (const double*)in, pl->d_four, pl->T, pl->nlat, pl->nhalf, C);
         REXI_HIP(hipGetLastError());
+        REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_INV, s));
         hipLaunchKernelGGL(k_fft_inverse, dim3(B * pl->nlat), dim3(256), lds, s, pl->d_four, (double*)out,
                            pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);
         REXI_HIP(hipGetLastError());

@@ -53,6 +53,8 @@ def load_library():
         "rexi_step_per_term": [P, P, P, c_int, P],
         "rexi_plan_autotune": [P, c_int, P, POINTER(c_int)],
         "rexi_plan_set_schedule": [P, c_int, c_int, POINTER(c_int)],
+        "rexi_plan_set_timing": [P, c_int],
+        "rexi_plan_kernel_time": [P, c_int, POINTER(c_double), POINTER(c_longlong)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -201,6 +203,17 @@ class Plan:
 
     def set_schedule(self, S: int, index: int):
         _check(self._lib.rexi_plan_set_schedule(self._h, S, index, None), "rexi_plan_set_schedule")
+
+    KERNEL_SOLVE, KERNEL_LEGENDRE_FWD, KERNEL_LEGENDRE_INV = 0, 1, 2
+
+    def set_timing(self, enable: bool):
+        _check(self._lib.rexi_plan_set_timing(self._h, int(enable)), "rexi_plan_set_timing")
+
+    def kernel_time(self, kernel: int):
+        """(total ms, launches) of one timed kernel since the last query."""
+        ms, n = c_double(0), c_longlong(0)
+        _check(self._lib.rexi_plan_kernel_time(self._h, kernel, byref(ms), byref(n)), "rexi_plan_kernel_time")
+        return ms.value, n.value
 
 
 def plan_for(w, **kw) -> Plan:
