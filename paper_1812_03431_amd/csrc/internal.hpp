@@ -76,10 +76,20 @@ struct Group {
     int pad;
 };
 
+// One launch of the solve kernel: items [item0, item0 + nitems) share the
+// elements-per-lane class SE and the cross-lane move kind.
+struct Launch {
+    int SE;
+    bool dpp;
+    int item0, nitems;
+    int pmax;  // largest lane group of the launch (sizes its LDS)
+};
+
 struct Schedule {
-    int SM = 4;       // elements per lane (template, even)
-    int ST = 1;       // states per wave (template)
+    int SM = 4;       // largest elements-per-lane class used
+    int ST = 1;       // states per work item
     int S = 0;        // states this schedule serves
+    std::vector<Launch> launches;
     std::vector<MInfo> minfo;
     std::vector<Item> items;
     std::vector<Group> groups;  // index ((m * 2 + p) * ntiles + tile)

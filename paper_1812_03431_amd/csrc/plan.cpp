@@ -15,7 +15,7 @@
 
 namespace rexi {
 
-bool solve_variant_supported(int SM, int ST);
+bool solve_variant_supported(int SE, bool dpp);
 int solve_waves_per_item();
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
                         hipStream_t s);
@@ -126,47 +126,98 @@ std::vector<MInfo> chain_layout(int T) {
     return mi;
 }
 
-// Work split of one candidate schedule.  Cost model per wave iteration
-// (64/P poles of one chain): s elements x (factorisation + 2 ST right-hand
-// sides) plus log2(P) cyclic-reduction levels.
-int build_schedule(rexi_plan* pl, int S, int SM, int ST, long long target_items, bool per_term, Schedule& out) {
+// Elements-per-lane class of a chain of L elements under a policy:
+//   0 "mixed": 8 (L <= 128), 12 (<= 192), 16 (<= 256), then 16 with bpermute
+//   1 "8/16" : 8 (L <= 128), 16 (<= 256), then 16 with bpermute
+//   2 "16"   : 16 (L <= 256), then 16 with bpermute
+//   3 "8"    : 8 (L <= 128), then 8 with bpermute (L <= 512), then 16 with bpermute
+//   4 "4"    : 4 with bpermute (L <= 256), then 8 / 16 with bpermute
+// Groups of at most 16 lanes move data with DPP row shifts.
+void tile_class(int policy, int L, int& SE, bool& dpp) {
+    dpp = true;
+    switch (policy) {
+        case 0:
+            if (L <= 128) { SE = 8; return; }
+            if (L <= 192) { SE = 12; return; }
+            if (L <= 256) { SE = 16; return; }
+            break;
+        case 1:
+            if (L <= 128) { SE = 8; return; }
+            if (L <= 256) { SE = 16; return; }
+            break;
+        case 2:
+            if (L <= 256) { SE = 16; return; }
+            break;
+        case 3:
+            if (L <= 128) { SE = 8; return; }
+            dpp = false;
+            if (L <= 512) { SE = 8; return; }
+            break;
+        default:
+            dpp = false;
+            if (L <= 256) { SE = 4; return; }
+            if (L <= 512) { SE = 8; return; }
+            break;
+    }
+    dpp = false;
+    SE = 16;
+}
+
+const char* kPolicyName[] = {"mixed", "8/16", "16", "8", "4"};
+constexpr int kPolicies = 5;
+
+// Work split of one candidate schedule.  Items are (m, chain, state, pole
+// range); the number of items per (m, chain, state) follows a cost model per
+// wave iteration (elements x sweep work + log2(P) reduction levels, scaled by
+// the waves a SIMD can hold for the class).  One launch per class; items in a
+// launch run longest first.
+int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, bool per_term, Schedule& out) {
     const int T = pl->T, N = per_term ? 1 : pl->N;
     out = Schedule();
-    out.SM = SM;
-    out.ST = ST;
+    out.ST = 1;
     out.S = S;
     out.minfo = chain_layout(T);
-    const int ntiles = (S + ST - 1) / ST;
-    struct Unit { int m, p, tile; double cost; int iters; int G; };
+    struct Unit { int m, p, tile; double cost; int iters; int G; int cls; };
     std::vector<Unit> units;
+    std::vector<std::pair<int, bool>> classes;
     double total = 0;
     for (int m = 0; m <= T; ++m) {
         MInfo& mi = out.minfo[m];
+        int SE;
+        bool dpp;
+        tile_class(policy, mi.L, SE, dpp);
+        if (!solve_variant_supported(SE, dpp)) return fail(REXI_EUNSUPPORTED, "tile class not compiled");
         int P = 1;
-        while (P * SM < mi.L) P *= 2;
-        if (P > 64) return fail(REXI_EUNSUPPORTED, "chain too long for this tiling");
+        while (P * SE < mi.L) P *= 2;
+        if (P > (dpp ? 16 : 64)) return fail(REXI_EUNSUPPORTED, "chain too long for this tiling");
         mi.P = P;
-        mi.s = SM;
+        mi.s = SE;
+        out.SM = std::max(out.SM, SE);
+        int cls = -1;
+        for (int c = 0; c < (int)classes.size(); ++c)
+            if (classes[c].first == SE && classes[c].second == dpp) cls = c;
+        if (cls < 0) { cls = (int)classes.size(); classes.push_back({SE, dpp}); }
         const int G = 64 / P * solve_waves_per_item();  // poles per workgroup iteration
         int lg = 0;
         while ((1 << lg) < P) ++lg;
-        const double it_cost = SM * (30.0 + 2 * ST * 30.0) + lg * (40.0 + 2 * ST * 10.0) + 30.0;
+        const double occ = SE <= 8 ? 2.0 : 1.0;
+        const double it_cost = (SE * 100.0 + lg * (dpp ? 90.0 : 160.0) + 60.0) / occ;
         const int iters = (N + G - 1) / G;
         for (int p = 0; p < 2; ++p)
-            for (int t = 0; t < ntiles; ++t) {
-                units.push_back({m, p, t, it_cost * iters, iters, G});
+            for (int t = 0; t < S; ++t) {
+                units.push_back({m, p, t, it_cost * iters, iters, G, cls});
                 total += it_cost * iters;
             }
     }
     const double target = per_term ? 1e300 : total / (double)std::max<long long>(1, target_items);
-    out.groups.assign((size_t)(T + 1) * 2 * ntiles, Group{0, 0, 0});
+    out.groups.assign((size_t)(T + 1) * 2 * S, Group{0, 0, 0});
     long long off = 0;
-    std::vector<std::pair<double, Item>> items;
+    std::vector<std::vector<std::pair<double, Item>>> by_class(classes.size());
     for (const Unit& u : units) {
         int nr = (int)std::lround(u.cost / target);
         nr = std::max(1, std::min(nr, u.iters));
-        const long long sz = (long long)ST * 2 * out.minfo[u.m].L;
-        Group& gr = out.groups[((size_t)u.m * 2 + u.p) * ntiles + u.tile];
+        const long long sz = 2LL * out.minfo[u.m].L;
+        Group& gr = out.groups[((size_t)u.m * 2 + u.p) * S + u.tile];
         gr.part_off = off;
         gr.nr = nr;
         for (int r = 0; r < nr; ++r) {
@@ -179,15 +230,23 @@ int build_schedule(rexi_plan* pl, int S, int SM, int ST, long long target_items,
             it.k1 = std::min(N, i1 * u.G);
             it.part_off = off;
             off += sz;
-            items.push_back({u.cost * (i1 - i0) / u.iters, it});
+            by_class[u.cls].push_back({u.cost * (i1 - i0) / u.iters, it});
         }
     }
-    std::stable_sort(items.begin(), items.end(),
-                     [](const std::pair<double, Item>& a, const std::pair<double, Item>& b) { return a.first > b.first; });
-    for (auto& x : items) out.items.push_back(x.second);
+    for (int c = 0; c < (int)classes.size(); ++c) {
+        auto& v = by_class[c];
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<double, Item>& a, const std::pair<double, Item>& b) {
+            return a.first > b.first;
+        });
+        int pmax = 1;
+        for (auto& x : v) pmax = std::max(pmax, out.minfo[x.second.m].P);
+        Launch L{classes[c].first, classes[c].second, (int)out.items.size(), (int)v.size(), pmax};
+        for (auto& x : v) out.items.push_back(x.second);
+        out.launches.push_back(L);
+    }
     out.part_size = off;
     char buf[96];
-    std::snprintf(buf, sizeof buf, "SM%d_ST%d_items%lld%s", SM, ST, (long long)out.items.size(),
+    std::snprintf(buf, sizeof buf, "%s_items%lld%s", kPolicyName[policy], (long long)out.items.size(),
                   per_term ? "_perterm" : "");
     out.name = buf;
     int rc = upload(&out.d_minfo, out.minfo);
@@ -220,34 +279,19 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
     }
     std::vector<Schedule>& c = pl->sched[S];
     if (c.empty()) {
-        const int sms[] = {4, 6, 8, 10, 12, 16};
-        const int sts[] = {1};
         const long long tg[] = {1024, 2048, 4096};
-        for (int SM : sms)
-            for (int ST : sts) {
-                if (!solve_variant_supported(SM, ST)) continue;
-                if (ST > S && ST > 1) continue;
-                for (long long t : tg) {
-                    Schedule sc;
-                    int rc = build_schedule(pl, S, SM, ST, t, false, sc);
-                    if (rc == REXI_EUNSUPPORTED) { free_schedule(sc); continue; }
-                    if (rc) { free_schedule(sc); return rc; }
-                    rc = ensure_part(pl, sc.part_size);
-                    if (rc) { free_schedule(sc); return rc; }
-                    c.push_back(sc);
-                }
+        for (int policy = 0; policy < kPolicies; ++policy)
+            for (long long t : tg) {
+                Schedule sc;
+                int rc = build_schedule(pl, S, policy, t, false, sc);
+                if (rc == REXI_EUNSUPPORTED) { free_schedule(sc); continue; }
+                if (rc) { free_schedule(sc); return rc; }
+                rc = ensure_part(pl, sc.part_size);
+                if (rc) { free_schedule(sc); return rc; }
+                c.push_back(sc);
             }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
-        // default until autotuned: 8 elements per lane, ~2048 work items
-        int best = 0;
-        for (int i = 0; i < (int)c.size(); ++i) {
-            const Schedule& s = c[i];
-            if (s.SM == 8) {
-                best = i;
-                if (s.items.size() >= 2048) break;
-            }
-        }
-        pl->chosen[S] = best;
+        pl->chosen[S] = 1;  // until autotuned: "mixed", ~2048 items
     }
     *out = &c;
     return REXI_OK;
@@ -546,7 +590,7 @@ int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* s
         if ((int)plan->per_term.size() <= S) plan->per_term.resize(S + 1);
         Schedule& sc = plan->per_term[S];
         if (sc.items.empty()) {
-            rc = build_schedule(plan, S, 4, 1, 0, true, sc);
+            rc = build_schedule(plan, S, 2, 0, true, sc);  // one tile class: one launch per pole
             if (rc) { free_schedule(sc); sc = Schedule(); return rc; }
         }
         if (sc.part_size > plan->acc_capacity) {

@@ -103,7 +103,8 @@ struct SolveArgs {
     long long var_stride, nspec;
 };
 
-constexpr int kWaves = 4;  // waves per workgroup; they share one item's staged data
+constexpr int kWaves = 4;   // waves per workgroup; they share one item's staged data
+constexpr int kStage = 12;  // doubles staged per chain position
 
 __device__ __forceinline__ cd crcp_newton(cd a) {
     // 1/(x + i y) = (x - i y)/(x^2 + y^2); the real reciprocal by v_rcp_f64 and
@@ -117,6 +118,56 @@ __device__ __forceinline__ cd crcp_newton(cd a) {
     return cd{a.r * r, -a.i * r};
 }
 
+// acc + conj(w x)
+__device__ __forceinline__ cd cfma_cj(cd acc, cd w, cd x) {
+    return cd{fma(w.r, x.r, fma(-w.i, x.i, acc.r)), fma(-w.r, x.i, fma(-w.i, x.r, acc.i))};
+}
+
+// Cross-lane moves inside a chain's lane group.  With DPP (groups of at most 16
+// lanes, aligned to the 16-lane rows) they are row shifts on the VALU:
+// row_shr:D gives lane i the value of lane i-D, row_shl:D that of lane i+D
+// (zero where the source lies outside the row).  Otherwise ds_bpermute.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <bool DPP, int D>
+struct Mover {
+    __device__ static __forceinline__ cd below(cd x, int lane) {  // value of lane - D
+        if constexpr (DPP) return cd{dpp_move<0x110 + D>(x.r), dpp_move<0x110 + D>(x.i)};
+        else return shfl(x, (lane - D) & 63);
+    }
+    __device__ static __forceinline__ cd above(cd x, int lane) {  // value of lane + D
+        if constexpr (DPP) return cd{dpp_move<0x100 + D>(x.r), dpp_move<0x100 + D>(x.i)};
+        else return shfl(x, (lane + D) & 63);
+    }
+};
+
+// One cyclic-reduction level with stride D: matrix row (A, B, C) and two
+// right-hand sides (Du, Dw).
+template <bool DPP, int D>
+__device__ __forceinline__ void pcr_level(cd& Ac, cd& Bc, cd& Cc, cd& Du, cd& Dw, int l, int P, int lane) {
+    typedef Mover<DPP, D> Mv;
+    const cd ib = crcp_newton(Bc);
+    const cd AL = Mv::below(Ac, lane), CL = Mv::below(Cc, lane), IL = Mv::below(ib, lane);
+    const cd DuL = Mv::below(Du, lane), DwL = Mv::below(Dw, lane);
+    const cd AR = Mv::above(Ac, lane), CR = Mv::above(Cc, lane), IR = Mv::above(ib, lane);
+    const cd DuR = Mv::above(Du, lane), DwR = Mv::above(Dw, lane);
+    // neighbours outside the chain's group: multipliers are zero (every lane
+    // holds finite values, so the products below vanish)
+    const cd k1 = (l >= D) ? cmul(Ac, IL) : mk(0, 0);
+    const cd k2 = (l + D < P) ? cmul(Cc, IR) : mk(0, 0);
+    Bc = cfms(cfms(Bc, k1, CL), k2, AR);
+    Du = cfms(cfms(Du, k1, DuL), k2, DuR);
+    Dw = cfms(cfms(Dw, k1, DwL), k2, DwR);
+    Ac = cneg(cmul(k1, AL));
+    Cc = cneg(cmul(k2, CR));
+}
+
 // One work item: chain p of order m, one state, a pole range.  SE elements per
 // lane (even, compile time); PH fixes the element types: element t of every
 // lane is a divergence element iff (t + PH) is odd.
@@ -128,9 +179,9 @@ __device__ __forceinline__ cd crcp_newton(cd a) {
 // pi_t = prod_{s<t} (-e_s), the back-substituted first elements
 // (y_0 = sum_t pi_t Y_t) that the left neighbour's interface row needs.  The
 // interface rows (one per lane) are solved by cyclic reduction across the
-// chain's P lanes, matrix and both right-hand sides in the same steps, and a
+// chain's P lanes, matrix and both right-hand sides in the same levels, and a
 // reverse sweep recovers the interior with both interface values.
-template <int SE, int PH, bool ACCUM>
+template <int SE, int PH, bool ACCUM, bool DPP>
 __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, const MInfo& mi, double* sm) {
     constexpr int NI = SE - 1;  // interior elements 0 .. SE-2; interface SE-1
     const int tid = threadIdx.x;
@@ -141,13 +192,13 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     const int st = it.tile;
     const int npos = P * SE;
 
-    // ---- stage the item's constants and right-hand side in LDS, [t][l] order:
-    // per position (th, om, cl, cr, rv.r, rv.i, rp.r, rp.i)
+    // ---- stage the item's constants and right-hand sides in LDS, [t][l] order:
+    // (th, om, cl, cr, rv, rp, rvw, rpw) with rvw = J conj(rv), rpw = J conj(rp)
     double* c = sm;
     for (int j = tid; j < npos; j += blockDim.x) {
         const int l2 = j / SE, t2 = j - l2 * SE;
         const int n = n0 + j;
-        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double v[kStage] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (j < L) {
             const long long i = mi.spec_off + (n - m);
             v[0] = A.th[i];
@@ -155,17 +206,22 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
             v[2] = (j > 0) ? A.cc[i] : 0.0;
             v[3] = (n < A.T) ? A.cc[i + 1] : 0.0;
             const double2 rv = A.ch_var[st * A.var_stride + mi.slot_base + (long long)p * L + j];
+            const double jv = (n & 1) ? 1.0 : -1.0;  // J on vorticity / divergence: -(-1)^n
             v[4] = rv.x;
             v[5] = rv.y;
+            v[8] = jv * rv.x;
+            v[9] = -jv * rv.y;
             if ((n + p) & 1) {
                 const double2 rp = A.ch_phi[st * A.nspec + i];
                 v[6] = rp.x;
                 v[7] = rp.y;
+                v[10] = jv * rp.x;
+                v[11] = -jv * rp.y;
             }
         }
-        double* o = c + (size_t)(t2 * P + l2) * 8;
+        double* o = c + (size_t)(t2 * P + l2) * kStage;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) o[r] = v[r];
+        for (int r = 0; r < kStage; ++r) o[r] = v[r];
     }
     __syncthreads();
 
@@ -178,9 +234,6 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
 #pragma unroll
     for (int t = 0; t < SE; ++t) av[t] = ap[t] = mk(0, 0);
 
-    const int src_dn = (lane + 1) & 63;
-    const int src_up = (lane + 63) & 63;
-    const bool lastl = (l == P - 1), firstl = (l == 0);
     const int stride = kWaves * G;
 
     for (int kb = it.k0; kb < it.k1; kb += stride) {
@@ -196,23 +249,21 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         double cbprev = 0.0;
         // element data of position t of this lane: diagonal b, couplings, RHS
         auto element = [&](int t, cd& b, double& ca, double& cb, cd& du, cd& dw) {
-            const double* o = c + (size_t)(t * P + l) * 8;
+            const double* o = c + (size_t)(t * P + l) * kStage;
             const double sg = ((PH + t) & 1) ? 1.0 : -1.0;
             ca = sg * o[2];
             cb = sg * o[3];
-            const cd rv = cd{o[4], o[5]};
-            const double jv = (t & 1) ? -jb : jb;
+            const cd rv = cd{o[4], o[5]}, rvw = cd{o[8], o[9]};
             if ((PH + t) & 1) {
                 const double om = o[1];
                 const cd f = cscale(ai, om);
                 b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, o[0]));
-                const cd rp = cd{o[6], o[7]};
-                du = cfms(rv, f, rp);
-                dw = cscale(cadd(cconj(rv), cmul(f, cconj(rp))), jv);
+                du = cfms(rv, f, cd{o[6], o[7]});
+                dw = cfma(rvw, f, cd{o[10], o[11]});
             } else {
                 b = mk(al.r, al.i + o[0]);
                 du = rv;
-                dw = cscale(cconj(rv), jv);
+                dw = rvw;
             }
         };
 #pragma unroll
@@ -241,44 +292,39 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
             cbprev = cb;
         }
 
-        // interface row -> tridiagonal system over the P lanes of the chain
+        // interface row -> tridiagonal system over the P lanes of the chain;
+        // the right neighbour's values enter with cI, which is zero at a chain end
         cd bI, dIu, dIw;
         double aI, cI;
         element(SE - 1, bI, aI, cI, dIu, dIw);
-        cd vN = shfl(v0, src_dn), wN = shfl(w0, src_dn);
-        cd guN = shfl(g0u, src_dn), gwN = shfl(g0w, src_dn);
-        if (lastl) vN = wN = guN = gwN = mk(0, 0);
+        typedef Mover<DPP, 1> M1;
+        const cd vN = M1::above(v0, lane), wN = M1::above(w0, lane);
+        const cd guN = M1::above(g0u, lane), gwN = M1::above(g0w, lane);
         cd Ac = cneg(cscale(gv[NI - 1], aI));
         cd Bc = csubs(csubs(bI, aI, e[NI - 1]), cI, vN);
         cd Cc = cneg(cscale(wN, cI));
         cd Du = csubs(csubs(dIu, aI, Gu[NI - 1]), cI, guN);
         cd Dw = csubs(csubs(dIw, aI, Gw[NI - 1]), cI, gwN);
 
-        // cyclic reduction: matrix and both right-hand sides together
-        for (int d = 1; d < P; d <<= 1) {
-            const cd ib = crcp_newton(Bc);
-            const int sl = (lane - d) & 63, sr = (lane + d) & 63;
-            const bool hl = l >= d, hr = l + d < P;
-            cd AL = shfl(Ac, sl), CL = shfl(Cc, sl), IL = shfl(ib, sl), DuL = shfl(Du, sl), DwL = shfl(Dw, sl);
-            cd AR = shfl(Ac, sr), CR = shfl(Cc, sr), IR = shfl(ib, sr), DuR = shfl(Du, sr), DwR = shfl(Dw, sr);
-            if (!hl) AL = CL = IL = DuL = DwL = mk(0, 0);
-            if (!hr) AR = CR = IR = DuR = DwR = mk(0, 0);
-            const cd k1 = cmul(Ac, IL), k2 = cmul(Cc, IR);
-            Bc = cfms(cfms(Bc, k1, CL), k2, AR);
-            Du = cfms(cfms(Du, k1, DuL), k2, DuR);
-            Dw = cfms(cfms(Dw, k1, DwL), k2, DwR);
-            Ac = cneg(cmul(k1, AL));
-            Cc = cneg(cmul(k2, CR));
+        // cyclic reduction over the lanes of the chain
+        if (1 < P) pcr_level<DPP, 1>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+        if (2 < P) pcr_level<DPP, 2>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+        if (4 < P) pcr_level<DPP, 4>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+        if (8 < P) pcr_level<DPP, 8>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+        if constexpr (!DPP) {
+            if (16 < P) pcr_level<DPP, 16>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            if (32 < P) pcr_level<DPP, 32>(Ac, Bc, Cc, Du, Dw, l, P, lane);
         }
         const cd iB = crcp_newton(Bc);
         const cd Xu = cmul(Du, iB), Xw = cmul(Dw, iB);
-        cd XLu = shfl(Xu, src_up), XLw = shfl(Xw, src_up);
-        if (firstl) XLu = XLw = mk(0, 0);
+        // the left neighbour's interface values (enter through gv, zero at a chain start)
+        const cd XLu = M1::below(Xu, lane), XLw = M1::below(Xw, lane);
 
-        // reverse sweep with both interface values; weighted sums
-        cd wx = cd{pd.wx.x, pd.wx.y}, wy = cd{pd.wy.x, pd.wy.y};
-        cd wxa = cd{pd.wxa.x, pd.wxa.y}, wya = cd{pd.wya.x, pd.wya.y};
-        if (!act) wx = wy = wxa = wya = mk(0, 0);
+        // reverse sweep with both interface values; weighted sums.  The J sign of
+        // the mirrored solve is folded into its weights per element parity.
+        cd wx = cd{pd.wx.x, pd.wx.y}, wxa = cd{pd.wxa.x, pd.wxa.y};
+        cd wyE = cscale(cd{pd.wy.x, pd.wy.y}, jb), wyaE = cscale(cd{pd.wya.x, pd.wya.y}, -jb);
+        if (!act) wx = wxa = wyE = wyaE = mk(0, 0);
         cd xu = Xu, xw = Xw;
 #pragma unroll
         for (int t = SE - 1; t >= 0; --t) {
@@ -287,9 +333,12 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
                 xw = cfms(cfms(Gw[t], XLw, gv[t]), e[t], xw);
             }
             if (vd[t]) {
-                const double jv = (t & 1) ? -jb : jb;
-                av[t] = cfma_conj(cfma(av[t], wx, xu), jv, wy, xw);
-                if ((PH + t) & 1) ap[t] = cfma_conj(cfma(ap[t], wxa, xu), -jv, wya, xw);
+                const cd wy = (t & 1) ? cneg(wyE) : wyE;
+                av[t] = cfma_cj(cfma(av[t], wx, xu), wy, xw);
+                if ((PH + t) & 1) {
+                    const cd wya = (t & 1) ? cneg(wyaE) : wyaE;
+                    ap[t] = cfma_cj(cfma(ap[t], wxa, xu), wya, xw);
+                }
             }
         }
     }
@@ -341,13 +390,13 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     }
 }
 
-template <int SE, bool ACCUM>
-__global__ void __launch_bounds__(256) k_solve(const SolveArgs A) {
+template <int SE, bool ACCUM, bool DPP>
+__global__ void __launch_bounds__(256) k_solve(const SolveArgs A, int item0) {
     extern __shared__ double sm[];
-    const Item it = A.items[blockIdx.x];
+    const Item it = A.items[item0 + blockIdx.x];
     const MInfo mi = A.minfo[it.m];
-    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM>(A, it, mi, sm);
-    else solve_item<SE, 0, ACCUM>(A, it, mi, sm);
+    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, DPP>(A, it, mi, sm);
+    else solve_item<SE, 0, ACCUM, DPP>(A, it, mi, sm);
 }
 
 // Layout conversion: physical state [S][3][nspec] -> chain layout, scaled.
@@ -456,33 +505,40 @@ __global__ void k_zero(double2* p, long long n) {
     if (gid < n) p[gid] = make_double2(0.0, 0.0);
 }
 
-template <int SE, bool ACC>
-hipError_t launch_solve_t(const SolveArgs& a, int nitems, hipStream_t s) {
-    const size_t lds = sizeof(double) * 8 * (size_t)(64 * SE);
-    hipLaunchKernelGGL((k_solve<SE, ACC>), dim3(nitems), dim3(64 * kWaves), lds, s, a);
+// LDS of one workgroup: the staged positions of the largest chain group.
+template <int SE, bool ACC, bool DPP>
+hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, hipStream_t s) {
+    const size_t lds = sizeof(double) * kStage * (size_t)(pmax * SE);
+    hipLaunchKernelGGL((k_solve<SE, ACC, DPP>), dim3(nitems), dim3(64 * kWaves), lds, s, a, item0);
     return hipGetLastError();
 }
 
 template <bool ACC>
-hipError_t launch_solve(int SE, int ST, const SolveArgs& a, int nitems, hipStream_t s) {
-    if (ST != 1) return hipErrorInvalidValue;
-    switch (SE) {
-        case 4: return launch_solve_t<4, ACC>(a, nitems, s);
-        case 6: return launch_solve_t<6, ACC>(a, nitems, s);
-        case 8: return launch_solve_t<8, ACC>(a, nitems, s);
-        case 10: return launch_solve_t<10, ACC>(a, nitems, s);
-        case 12: return launch_solve_t<12, ACC>(a, nitems, s);
-        case 16: return launch_solve_t<16, ACC>(a, nitems, s);
+hipError_t launch_solve(const Launch& L, const SolveArgs& a, hipStream_t s) {
+    if (L.nitems <= 0) return hipSuccess;
+    if (L.pmax > (L.dpp ? 16 : 64)) return hipErrorInvalidValue;
+    if (L.dpp) {
+        switch (L.SE) {
+            case 8: return launch_solve_t<8, ACC, true>(a, L.item0, L.nitems, L.pmax, s);
+            case 12: return launch_solve_t<12, ACC, true>(a, L.item0, L.nitems, L.pmax, s);
+            case 16: return launch_solve_t<16, ACC, true>(a, L.item0, L.nitems, L.pmax, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (L.SE) {
+        case 4: return launch_solve_t<4, ACC, false>(a, L.item0, L.nitems, L.pmax, s);
+        case 8: return launch_solve_t<8, ACC, false>(a, L.item0, L.nitems, L.pmax, s);
+        case 16: return launch_solve_t<16, ACC, false>(a, L.item0, L.nitems, L.pmax, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// Tilings compiled into the library (elements per lane x states per wave).
-// Larger tiles exceed the register file and spill to scratch memory.
-bool solve_variant_supported(int SE, int ST) {
-    return ST == 1 && (SE == 4 || SE == 6 || SE == 8 || SE == 10 || SE == 12 || SE == 16);
+// Tilings compiled into the library: elements per lane, and whether the
+// lane group fits a 16-lane row (DPP moves) or needs ds_bpermute.
+bool solve_variant_supported(int SE, bool dpp) {
+    return dpp ? (SE == 8 || SE == 12 || SE == 16) : (SE == 4 || SE == 8 || SE == 16);
 }
 int solve_waves_per_item() { return kWaves; }
 
@@ -512,7 +568,11 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
     a.S = S;
     a.var_stride = pl->nslots + 2;
     a.nspec = pl->nspec;
-    return launch_solve<false>(sc.SM, sc.ST, a, (int)sc.items.size(), s);
+    for (const Launch& L : sc.launches) {
+        hipError_t e = launch_solve<false>(L, a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,
@@ -569,7 +629,11 @@ hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int b
     a.S = S;
     a.var_stride = pl->nslots + 2;
     a.nspec = pl->nspec;
-    return launch_solve<true>(sc.SM, sc.ST, a, (int)sc.items.size(), s);
+    for (const Launch& L : sc.launches) {
+        hipError_t e = launch_solve<true>(L, a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rexi
