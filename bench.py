@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--schedule", type=int, default=-1, help="use this schedule index instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -136,8 +137,13 @@ def main():
 
     grid = torch.from_numpy(synth.random_grid(w.nlat, w.nlon, B, 0)).to(dev)
     target = torch.from_numpy(synth.random_state(T, S, 100)[:, 0].copy()).to(dev)
-    if not args.no_autotune:
-        plan.autotune(S)
+    if args.schedule >= 0:
+        plan.set_schedule(S, args.schedule)
+        chosen = args.schedule
+    elif not args.no_autotune:
+        chosen = plan.autotune(S)
+    else:
+        chosen = None
     torch.cuda.synchronize()
 
     def job():
@@ -219,6 +225,7 @@ def main():
         "config": {"workload": w.name, "T": T, "grid": f"{w.nlon}x{w.nlat}", "dt_s": w.dt, "M": w.M,
                    "h": w.h, "poles": N, "states": S, "forward_steps": w.steps, "adjoint_steps": w.steps,
                    "checkpoint_every": ck, "sh_fields": B, "blocks_per_step": blocks_per_job},
+        "schedule": chosen,
         "rexi_step_ms": avg_solve_s * 1e3,
         "fwd_plus_adjoint_step_ms": 2 * avg_solve_s * 1e3,
         "batched_step_ms": batched_ms,
@@ -231,11 +238,13 @@ def main():
         "legendre": leg,
     }
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        # one elementwise kernel that reads 1 GiB and writes 1 GiB: the scale of
+        # the FETCH_SIZE / WRITE_SIZE counters for known traffic
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         a.fill_(1.0)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:

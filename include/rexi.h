@@ -167,9 +167,16 @@ int rexi_plan_autotune(rexi_plan *plan, int S, void *stream, int *chosen);
  * number of candidates. */
 int rexi_plan_set_schedule(rexi_plan *plan, int S, int index, int *count);
 
+/* Step graphs.  By default every step is replayed as a captured HIP graph
+ * (solve launches + reduction), built on first use per (S, direction, buffer)
+ * and rebuilt after a schedule change; enable = 0 makes the plan launch the
+ * kernels one by one instead.  Results are identical either way. */
+int rexi_plan_set_graphs(rexi_plan *plan, int enable);
+
 /* Kernel timing for measurement.  rexi_plan_set_timing(plan, 1) makes the plan
  * bracket every later launch of the timed kernels with a HIP event pair on the
- * launch stream; 0 stops recording.  rexi_plan_kernel_time synchronises on the
+ * launch stream (steps then run as individual launches, not graphs); 0 stops
+ * recording.  rexi_plan_kernel_time synchronises on the
  * recorded events and returns the summed elapsed time (ms) and the number of
  * launches of one kernel since the last query, then forgets them.
  *   kernel  REXI_KERNEL_SOLVE (fused banded solve), REXI_KERNEL_LEGENDRE_FWD,

@@ -85,7 +85,10 @@ struct Launch {
     int pmax;  // largest lane group of the launch (sizes its LDS)
 };
 
+constexpr int kMaxLaunches = 8;  // solve launches per step (tile classes)
+
 struct Schedule {
+    bool persistent = false;  // resident grid + atomic work counter per launch
     int SM = 4;       // largest elements-per-lane class used
     int ST = 1;       // states per work item
     int S = 0;        // states this schedule serves
@@ -143,6 +146,20 @@ struct rexi_plan {
     void* d_tiles_f = nullptr;    // Legendre tiles, forward / inverse
     void* d_tiles_i = nullptr;
     int ntiles_f = 0, ntiles_i = 0;
+
+    // persistent launches: one work counter per solve launch
+    int* d_counters = nullptr;
+    // captured step graphs: key (S, adjoint, input buffer), valid for `graph_gen`
+    struct StepGraph {
+        const rexi::Schedule* sched;
+        int S, adjoint, buf;
+        long long gen;
+        hipGraphExec_t exec;
+    };
+    std::vector<StepGraph> graphs;
+    long long graph_gen = 0;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
 
     // measurement: event pairs around timed launches, per kernel kind
     bool timing = false;

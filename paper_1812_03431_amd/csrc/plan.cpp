@@ -23,6 +23,8 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
 hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,
                           void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s);
 hipError_t enqueue_zero(double2* p, long long n, hipStream_t s);
+hipError_t enqueue_finish(rexi_plan* pl, int buf, void* u, int S, int adjoint, const MInfo* d_layout,
+                          hipStream_t s);
 hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int buf, int S, hipStream_t s);
 int sh_setup(rexi_plan* pl);
 void sh_release(rexi_plan* pl);
@@ -197,7 +199,7 @@ int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, boo
         for (int c = 0; c < (int)classes.size(); ++c)
             if (classes[c].first == SE && classes[c].second == dpp) cls = c;
         if (cls < 0) { cls = (int)classes.size(); classes.push_back({SE, dpp}); }
-        const int G = 64 / P * solve_waves_per_item();  // poles per workgroup iteration
+        const int G = 64 / P * (per_term ? 1 : solve_waves_per_item());  // poles per workgroup iteration
         int lg = 0;
         while ((1 << lg) < P) ++lg;
         const double occ = SE <= 8 ? 2.0 : 1.0;
@@ -261,8 +263,15 @@ void free_schedule(Schedule& s) {
     dev_free(s.d_groups);
 }
 
+void drop_graphs(rexi_plan* pl) {
+    for (auto& g : pl->graphs) (void)hipGraphExecDestroy(g.exec);
+    pl->graphs.clear();
+    ++pl->graph_gen;
+}
+
 int ensure_part(rexi_plan* pl, long long n) {
     if (n <= pl->part_capacity) return REXI_OK;
+    drop_graphs(pl);
     dev_free(pl->d_part);
     pl->part_capacity = 0;
     int rc = dev_alloc(&pl->d_part, (size_t)n);
@@ -280,18 +289,22 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
     std::vector<Schedule>& c = pl->sched[S];
     if (c.empty()) {
         const long long tg[] = {1024, 2048, 4096};
-        for (int policy = 0; policy < kPolicies; ++policy)
-            for (long long t : tg) {
-                Schedule sc;
-                int rc = build_schedule(pl, S, policy, t, false, sc);
-                if (rc == REXI_EUNSUPPORTED) { free_schedule(sc); continue; }
-                if (rc) { free_schedule(sc); return rc; }
-                rc = ensure_part(pl, sc.part_size);
-                if (rc) { free_schedule(sc); return rc; }
-                c.push_back(sc);
-            }
+        for (int persistent = 0; persistent < 2; ++persistent)
+            for (int policy = 0; policy < kPolicies; ++policy)
+                for (long long t : tg) {
+                    Schedule sc;
+                    int rc = build_schedule(pl, S, policy, t, false, sc);
+                    if (rc == REXI_EUNSUPPORTED) { free_schedule(sc); continue; }
+                    if (rc) { free_schedule(sc); return rc; }
+                    if ((int)sc.launches.size() > kMaxLaunches) { free_schedule(sc); continue; }
+                    sc.persistent = persistent != 0;
+                    if (sc.persistent) sc.name = "persistent_" + sc.name;
+                    rc = ensure_part(pl, sc.part_size);
+                    if (rc) { free_schedule(sc); return rc; }
+                    c.push_back(sc);
+                }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
-        pl->chosen[S] = 1;  // until autotuned: "mixed", ~2048 items
+        pl->chosen[S] = 2;  // until autotuned: "mixed", ~4096 items
     }
     *out = &c;
     return REXI_OK;
@@ -314,6 +327,33 @@ int check_state_call(rexi_plan* pl, const void* in, const void* out, int S, int 
     return REXI_OK;
 }
 
+// The graph of one step for (S, direction, input buffer): solve launches and
+// the reduction into the other chain buffer, captured on the plan's stream.
+int step_graph(rexi_plan* pl, const Schedule& sc, int S, int adjoint, int buf, hipGraphExec_t* out) {
+    for (auto& g : pl->graphs)
+        if (g.sched == &sc && g.S == S && g.adjoint == adjoint && g.buf == buf && g.gen == pl->graph_gen) {
+            *out = g.exec;
+            return REXI_OK;
+        }
+    hipGraph_t graph = nullptr;
+    REXI_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = enqueue_solve(pl, sc, buf, S, adjoint, pl->cap_stream);
+    hipError_t e2 = hipSuccess;
+    if (e1 == hipSuccess)
+        e2 = enqueue_reduce(pl, sc, pl->d_part, buf, buf ^ 1, nullptr, S, adjoint, pl->d_slot_m, pl->cap_stream);
+    hipError_t e3 = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (e1 != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e1, "capture solve"); }
+    if (e2 != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e2, "capture reduce"); }
+    if (e3 != hipSuccess) return hip_fail(e3, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e4 != hipSuccess) return hip_fail(e4, "hipGraphInstantiate");
+    pl->graphs.push_back({&sc, S, adjoint, buf, pl->graph_gen, exec});
+    *out = exec;
+    return REXI_OK;
+}
+
 int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S, int nsteps, int adjoint,
               hipStream_t s) {
     const size_t bytes = (size_t)S * 3 * pl->nspec * 16;
@@ -323,6 +363,18 @@ int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S
     }
     REXI_HIP(enqueue_prep(pl, u0, 0, S, adjoint, pl->sched_layout, s));
     int cur = 0;
+    if (pl->use_graphs && !pl->timing) {
+        // captured step graphs (solve + reduction), then the final layout change
+        for (int k = 0; k < nsteps; ++k) {
+            hipGraphExec_t exec = nullptr;
+            int rc = step_graph(pl, sc, S, adjoint, cur, &exec);
+            if (rc) return rc;
+            REXI_HIP(hipGraphLaunch(exec, s));
+            cur ^= 1;
+        }
+        REXI_HIP(enqueue_finish(pl, cur, u1, S, adjoint, pl->sched_layout, s));
+        return REXI_OK;
+    }
     for (int k = 0; k < nsteps; ++k) {
         const bool last = (k == nsteps - 1);
         REXI_HIP(timed_begin(pl, REXI_KERNEL_SOLVE, s));
@@ -362,6 +414,10 @@ void drop_events(rexi_plan* pl) {
 
 void release(rexi_plan* pl) {
     drop_events(pl);
+    drop_graphs(pl);
+    dev_free(pl->d_counters);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    pl->cap_stream = nullptr;
     for (auto& c : pl->sched)
         for (auto& s : c) free_schedule(s);
     for (auto& s : pl->per_term) free_schedule(s);
@@ -485,6 +541,15 @@ int create(const rexi_params* p, rexi_plan** out) {
         rc = dev_alloc(&pl->d_ch_var[d], (size_t)p->max_states * (pl->nslots + 2));
         if (!rc) rc = dev_alloc(&pl->d_ch_phi[d], (size_t)p->max_states * pl->nspec);
     }
+    if (!rc) rc = dev_alloc(&pl->d_counters, kMaxLaunches);
+    if (!rc) {
+        hipError_t e = hipMemset(pl->d_counters, 0, kMaxLaunches * sizeof(int));
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemset");
+    }
+    if (!rc) {
+        hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamCreateWithFlags");
+    }
     if (!rc && p->nlat > 0) rc = sh_setup(pl);
     if (rc) {
         release(pl);
@@ -590,7 +655,7 @@ int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* s
         if ((int)plan->per_term.size() <= S) plan->per_term.resize(S + 1);
         Schedule& sc = plan->per_term[S];
         if (sc.items.empty()) {
-            rc = build_schedule(plan, S, 2, 0, true, sc);  // one tile class: one launch per pole
+            rc = build_schedule(plan, S, 3, 0, true, sc);  // 8 elements per lane, one wave per chain
             if (rc) { free_schedule(sc); sc = Schedule(); return rc; }
         }
         if (sc.part_size > plan->acc_capacity) {
@@ -620,6 +685,7 @@ int rexi_plan_set_schedule(rexi_plan* plan, int S, int index, int* count) {
     if (count) *count = (int)c->size();
     if (index < 0) return REXI_OK;
     if (index >= (int)c->size()) return fail(REXI_EINVAL, "schedule index out of range");
+    if (plan->chosen[S] != index) drop_graphs(plan);
     plan->chosen[S] = index;
     return REXI_OK;
 }
@@ -666,8 +732,15 @@ int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
     (void)hipFree(u0);
     (void)hipFree(u1);
     if (rc) return rc;
+    if (plan->chosen[S] != best) drop_graphs(plan);
     plan->chosen[S] = best;
     if (chosen) *chosen = best;
+    return REXI_OK;
+}
+
+int rexi_plan_set_graphs(rexi_plan* plan, int enable) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    plan->use_graphs = enable != 0;
     return REXI_OK;
 }
 

@@ -38,6 +38,8 @@
 // results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace rexi {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void pcr_level(cd& Ac, cd& Bc, cd& Cc, cd& Du, cd& Dw
 // interface rows (one per lane) are solved by cyclic reduction across the
 // chain's P lanes, matrix and both right-hand sides in the same levels, and a
 // reverse sweep recovers the interior with both interface values.
-template <int SE, int PH, bool ACCUM, bool DPP>
+template <int SE, int PH, bool ACCUM, bool DPP, int W>
 __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, const MInfo& mi, double* sm) {
     constexpr int NI = SE - 1;  // interior elements 0 .. SE-2; interface SE-1
     const int tid = threadIdx.x;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
 #pragma unroll
     for (int t = 0; t < SE; ++t) av[t] = ap[t] = mk(0, 0);
 
-    const int stride = kWaves * G;
+    const int stride = W * G;
 
     for (int kb = it.k0; kb < it.k1; kb += stride) {
         if (kb + wave * G >= it.k1) continue;  // this wave has no pole left (uniform)
@@ -355,7 +357,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     // then the waves, in order, through LDS (reusing the staging area)
     __syncthreads();
     double2* acc = reinterpret_cast<double2*>(sm);  // [2][SE][P]
-    for (int wv = 0; wv < kWaves; ++wv) {
+    for (int wv = 0; wv < W; ++wv) {
         if (wave == wv && g == 0) {
 #pragma unroll
             for (int t = 0; t < SE; ++t) {
@@ -390,13 +392,37 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     }
 }
 
-template <int SE, bool ACCUM, bool DPP>
-__global__ void __launch_bounds__(256) k_solve(const SolveArgs A, int item0) {
-    extern __shared__ double sm[];
-    const Item it = A.items[item0 + blockIdx.x];
+template <int SE, bool ACCUM, bool DPP, int W>
+__device__ __forceinline__ void run_item(const SolveArgs& A, int idx, double* sm) {
+    const Item it = A.items[idx];
     const MInfo mi = A.minfo[it.m];
-    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, DPP>(A, it, mi, sm);
-    else solve_item<SE, 0, ACCUM, DPP>(A, it, mi, sm);
+    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, DPP, W>(A, it, mi, sm);
+    else solve_item<SE, 0, ACCUM, DPP, W>(A, it, mi, sm);
+}
+
+// One workgroup per item (counter == null), or persistent: a grid of resident
+// workgroups takes items [item0, item0 + nitems) from an atomic counter that
+// starts at zero, until none is left (every workgroup then leaves the loop).
+template <int SE, bool ACCUM, bool DPP, int W>
+__global__ void __launch_bounds__(64 * W) k_solve(const SolveArgs A, int item0, int nitems, int* counter) {
+    extern __shared__ double sm[];
+    if (counter == nullptr) {
+        run_item<SE, ACCUM, DPP, W>(A, item0 + blockIdx.x, sm);
+        return;
+    }
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int i = next;
+        __syncthreads();
+        if (i < 0 || i >= nitems) break;
+        run_item<SE, ACCUM, DPP, W>(A, item0 + i, sm);
+    }
+}
+
+__global__ void k_reset_counters(int* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
 // Layout conversion: physical state [S][3][nspec] -> chain layout, scaled.
@@ -500,35 +526,75 @@ __global__ void k_reduce(const ReduceArgs R) {
     }
 }
 
+// Chain layout (scaled) -> physical state [S][3][nspec].
+__global__ void k_finish(const double2* __restrict__ ch_var, const double2* __restrict__ ch_phi,
+                         double2* __restrict__ u, const MInfo* __restrict__ minfo, const int* __restrict__ idx_n,
+                         const int* __restrict__ idx_m, const double* __restrict__ sc, int invert_scale, int S,
+                         long long nspec, long long var_stride, long long nslots) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)S * nspec) return;
+    const int st = (int)(gid / nspec);
+    const long long i = gid - (long long)st * nspec;
+    double2* us = u + (long long)st * 3 * nspec;
+    us[i] = ch_phi[st * nspec + i];
+    if (i == 0) {
+        us[nspec] = ch_var[st * var_stride + nslots];
+        us[2 * nspec] = ch_var[st * var_stride + nslots + 1];
+        return;
+    }
+    const int n = idx_n[i], m = idx_m[i];
+    const MInfo mi = minfo[m];
+    const double f = invert_scale ? sc[i] : 1.0 / sc[i];
+    const long long pz = n & 1, pd = (n + 1) & 1;
+    const double2 z = ch_var[st * var_stride + mi.slot_base + pz * mi.L + (n - mi.n0)];
+    const double2 dv = ch_var[st * var_stride + mi.slot_base + pd * mi.L + (n - mi.n0)];
+    us[nspec + i] = make_double2(z.x * f, z.y * f);
+    us[2 * nspec + i] = make_double2(dv.x * f, dv.y * f);
+}
+
 __global__ void k_zero(double2* p, long long n) {
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid < n) p[gid] = make_double2(0.0, 0.0);
 }
 
 // LDS of one workgroup: the staged positions of the largest chain group.
+// The batched form runs kWaves waves per workgroup (sharing the staged data of
+// an item); the per-term form (ACC) one wave per chain.
 template <int SE, bool ACC, bool DPP>
-hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, hipStream_t s) {
+hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, int* counter, hipStream_t s) {
+    constexpr int W = ACC ? 1 : kWaves;
     const size_t lds = sizeof(double) * kStage * (size_t)(pmax * SE);
-    hipLaunchKernelGGL((k_solve<SE, ACC, DPP>), dim3(nitems), dim3(64 * kWaves), lds, s, a, item0);
+    int grid = nitems;
+    if (counter) {
+        // resident workgroups of this kernel on the whole device
+        int dev = 0, ncu = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<SE, ACC, DPP, W>, 64 * W, lds);
+        if (e != hipSuccess) return e;
+        grid = std::max(1, std::min(nitems, std::max(1, per_cu) * ncu));
+    }
+    hipLaunchKernelGGL((k_solve<SE, ACC, DPP, W>), dim3(grid), dim3(64 * W), lds, s, a, item0, nitems, counter);
     return hipGetLastError();
 }
 
 template <bool ACC>
-hipError_t launch_solve(const Launch& L, const SolveArgs& a, hipStream_t s) {
+hipError_t launch_solve(const Launch& L, const SolveArgs& a, int* counter, hipStream_t s) {
     if (L.nitems <= 0) return hipSuccess;
     if (L.pmax > (L.dpp ? 16 : 64)) return hipErrorInvalidValue;
     if (L.dpp) {
         switch (L.SE) {
-            case 8: return launch_solve_t<8, ACC, true>(a, L.item0, L.nitems, L.pmax, s);
-            case 12: return launch_solve_t<12, ACC, true>(a, L.item0, L.nitems, L.pmax, s);
-            case 16: return launch_solve_t<16, ACC, true>(a, L.item0, L.nitems, L.pmax, s);
+            case 8: return launch_solve_t<8, ACC, true>(a, L.item0, L.nitems, L.pmax, counter, s);
+            case 12: return launch_solve_t<12, ACC, true>(a, L.item0, L.nitems, L.pmax, counter, s);
+            case 16: return launch_solve_t<16, ACC, true>(a, L.item0, L.nitems, L.pmax, counter, s);
             default: return hipErrorInvalidValue;
         }
     }
     switch (L.SE) {
-        case 4: return launch_solve_t<4, ACC, false>(a, L.item0, L.nitems, L.pmax, s);
-        case 8: return launch_solve_t<8, ACC, false>(a, L.item0, L.nitems, L.pmax, s);
-        case 16: return launch_solve_t<16, ACC, false>(a, L.item0, L.nitems, L.pmax, s);
+        case 4: return launch_solve_t<4, ACC, false>(a, L.item0, L.nitems, L.pmax, counter, s);
+        case 8: return launch_solve_t<8, ACC, false>(a, L.item0, L.nitems, L.pmax, counter, s);
+        case 16: return launch_solve_t<16, ACC, false>(a, L.item0, L.nitems, L.pmax, counter, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -568,8 +634,15 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
     a.S = S;
     a.var_stride = pl->nslots + 2;
     a.nspec = pl->nspec;
-    for (const Launch& L : sc.launches) {
-        hipError_t e = launch_solve<false>(L, a, s);
+    if (sc.persistent) {
+        const int n = (int)sc.launches.size();
+        if (n > kMaxLaunches) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, pl->d_counters, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (size_t c = 0; c < sc.launches.size(); ++c) {
+        hipError_t e = launch_solve<false>(sc.launches[c], a, sc.persistent ? pl->d_counters + c : nullptr, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -606,6 +679,16 @@ hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part
     return hipGetLastError();
 }
 
+hipError_t enqueue_finish(rexi_plan* pl, int buf, void* u, int S, int adjoint, const MInfo* d_layout,
+                          hipStream_t s) {
+    const long long n = (long long)S * pl->nspec;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, pl->d_ch_var[buf],
+                       pl->d_ch_phi[buf], (double2*)u, d_layout, pl->d_idx_n, pl->d_idx_m, pl->d_sc, adjoint, S,
+                       pl->nspec, pl->nslots + 2, pl->nslots);
+    return hipGetLastError();
+}
+
 hipError_t enqueue_zero(double2* p, long long n, hipStream_t s) {
     const int bs = 256;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, p, n);
@@ -630,7 +713,7 @@ hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int b
     a.var_stride = pl->nslots + 2;
     a.nspec = pl->nspec;
     for (const Launch& L : sc.launches) {
-        hipError_t e = launch_solve<true>(L, a, s);
+        hipError_t e = launch_solve<true>(L, a, nullptr, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -15,6 +15,7 @@
 // Workspace layout of the Fourier coefficients: Fw[m][j][c], c = 2b + {0: re, 1: im}.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -23,6 +24,8 @@ namespace rexi {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr size_t kLdsBytes = 64 * 1024;  // LDS per workgroup used by the Legendre kernels
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
@@ -104,99 +107,160 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
     for (int k = threadIdx.x; k < nlon; k += blockDim.x) dst[k] = X[k].x;
 }
 
-// A tile of the Legendre contraction: order m, parity e (n - m even/odd),
-// 16 consecutive degrees of that parity starting at index i0 (forward) or 16
-// latitudes starting at j0 (inverse).
-struct LegTile {
-    int m, e, i0, pad;
+// A run of Legendre tiles of one order m for one workgroup of four waves.
+// Forward: tiles [t0, t1) over the even-parity degree tiles followed by the
+// odd ones (16 degrees each), two per wave.  Inverse: tiles of 16
+// latitudes, one per wave.
+struct LegWork {
+    int m, t0, t1, pad;
 };
 
-// Forward: out[b][idx(m, n)] = sum_{j<H} P[m][n][j] w_j (F_j +- F_j')  (+ even, - odd)
-__global__ void __launch_bounds__(64) k_legendre_forward(const LegTile* __restrict__ tiles,
-                                                         const double* __restrict__ plm,
-                                                         const double* __restrict__ wts,
-                                                         const double* __restrict__ Fw, double* __restrict__ spec,
-                                                         int T, int nlat, int H, int C) {
-    const LegTile tl = tiles[blockIdx.x];
-    const int lane = threadIdx.x;
-    const int m = tl.m, e = tl.e;
+// Forward: out[b][idx(m, n)] = sum_{j<H} P[m][n][j] w_j (F_j +- F_j')  (+ even, - odd).
+// The weighted even/odd Fourier blocks of m, E and O [H][C], are staged in
+// LDS once per workgroup.  MFMA k index: within a block of 16 latitudes J,
+// lane group kq at k-step s takes latitude J + 4 kq + s, so each lane reads
+// four consecutive table entries of its degree.  Each wave keeps four
+// independent accumulators (two degree tiles x two column tiles) in flight.
+__global__ void __launch_bounds__(256) k_legendre_forward(const LegWork* __restrict__ work,
+                                                          const double* __restrict__ plm,
+                                                          const double* __restrict__ wts,
+                                                          const double* __restrict__ Fw, double* __restrict__ spec,
+                                                          int T, int nlat, int H, int Cs, int c_off, int C) {
+    // columns [c_off, c_off + C) of the Fourier block (row stride Cs)
+    extern __shared__ double lds[];
+    const LegWork wk = work[blockIdx.x];
+    const int m = wk.m;
+    double* E = lds;            // [H][C]
+    double* O = lds + H * C;    // [H][C]
+    for (int idx = threadIdx.x; idx < H * C; idx += blockDim.x) {
+        const int j = idx / C, c = idx - j * C;
+        const double f1 = Fw[((long long)m * nlat + j) * Cs + c_off + c];
+        const double f2 = Fw[((long long)m * nlat + (nlat - 1 - j)) * Cs + c_off + c];
+        E[idx] = wts[j] * (f1 + f2);
+        O[idx] = wts[j] * (f1 - f2);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long so = spec_offset(T, m);
+    const long long ns = nspec_of(T);
+    const int L = T + 1 - m;
+    const int ne = ((L + 1) / 2 + 15) / 16;  // even-parity tiles
     const int row = lane & 15, kq = lane >> 4;
-    const int n_a = m + e + 2 * (tl.i0 + row);  // degree of this lane's A row
-    const bool row_ok = n_a <= T;
-    const double* prow = plm + (so + (row_ok ? n_a - m : 0)) * H;
-    const double sgn = e ? -1.0 : 1.0;
-    for (int c0 = 0; c0 < C; c0 += 16) {
-        const int col = c0 + (lane & 15);
-        const bool col_ok = col < C;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int j0 = 0; j0 < H; j0 += 4) {
-            const int j = j0 + kq;
-            double a = 0.0, bv = 0.0;
-            if (j < H) {
-                if (row_ok) a = prow[j];
-                if (col_ok) {
-                    const double f1 = Fw[((long long)m * nlat + j) * C + col];
-                    const double f2 = Fw[((long long)m * nlat + (nlat - 1 - j)) * C + col];
-                    bv = wts[j] * fma(sgn, f2, f1);
+    for (int tb = wk.t0 + 2 * wave; tb < wk.t1; tb += 8) {
+        int e[2], i0[2], nrow[2];
+        bool rok[2];
+        const double* prow[2];
+        const double* B[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = tb + u;
+            const bool tile_ok = t < wk.t1;
+            e[u] = (tile_ok && t >= ne) ? 1 : 0;
+            i0[u] = tile_ok ? (t - (e[u] ? ne : 0)) * 16 : 0;
+            nrow[u] = m + e[u] + 2 * (i0[u] + row);
+            rok[u] = tile_ok && nrow[u] <= T;
+            prow[u] = plm + (so + (rok[u] ? nrow[u] - m : 0)) * H;
+            B[u] = e[u] ? O : E;
+        }
+        for (int c0 = 0; c0 < C; c0 += 32) {
+            const int col0 = c0 + (lane & 15), col1 = col0 + 16;
+            const bool ok0 = col0 < C, ok1 = col1 < C;
+            v4d acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
+                             {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
+            for (int J = 0; J < H; J += 16) {
+                const int jb = J + 4 * kq;
+                double a[2][4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) a[u][s] = (rok[u] && jb + s < H) ? prow[u][jb + s] : 0.0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const bool jok = jb + s < H;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const double b0 = (ok0 && jok) ? B[u][(jb + s) * C + col0] : 0.0;
+                        const double b1 = (ok1 && jok) ? B[u][(jb + s) * C + col1] : 0.0;
+                        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b0, acc[u][0], 0, 0, 0);
+                        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b1, acc[u][1], 0, 0, 0);
+                    }
                 }
             }
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
-        }
-        // accumulator register r of lane l holds D[4 r + l/16][l % 16]
-        if (col_ok) {
-            const int b = col >> 1, ri = col & 1;
+            // accumulator register r of lane l holds D[4 r + l/16][l % 16]
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * r + kq;
-                const int n = m + e + 2 * (tl.i0 + i);
-                if (n <= T) spec[((long long)b * nspec_of(T) + so + (n - m)) * 2 + ri] = acc[r];
-            }
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int col = h ? col1 : col0;
+                    if (!(h ? ok1 : ok0) || tb + u >= wk.t1) continue;
+                    const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = m + e[u] + 2 * (i0[u] + 4 * r + kq);
+                        if (n <= T) spec[((long long)b * ns + so + (n - m)) * 2 + ri] = acc[u][h][r];
+                    }
+                }
         }
     }
 }
 
 // Inverse: for 16 latitudes j (< H): Fe = sum_{n-m even} P S, Fo = sum_{odd} P S;
-// Fw[m][j] = Fe + Fo, Fw[m][j'] = Fe - Fo.
-__global__ void __launch_bounds__(64) k_legendre_inverse(const LegTile* __restrict__ tiles,
-                                                         const double* __restrict__ plm,
-                                                         const double* __restrict__ spec,
-                                                         double* __restrict__ Fw, int T, int nlat, int H, int C) {
-    const LegTile tl = tiles[blockIdx.x];
-    const int lane = threadIdx.x;
-    const int m = tl.m;
+// Fw[m][j] = Fe + Fo, Fw[m][j'] = Fe - Fo.  The spectral block of m, [L][C],
+// is staged in LDS once per workgroup; each wave keeps four independent
+// accumulators (two parities x two column tiles) in flight.
+__global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restrict__ work,
+                                                          const double* __restrict__ plm,
+                                                          const double* __restrict__ spec,
+                                                          double* __restrict__ Fw, int T, int nlat, int H, int Cs,
+                                                          int c_off, int C) {
+    extern __shared__ double lds[];
+    const LegWork wk = work[blockIdx.x];
+    const int m = wk.m;
     const long long so = spec_offset(T, m);
     const long long ns = nspec_of(T);
     const int L = T + 1 - m;
-    const int jrow = tl.i0 + (lane & 15);  // A row = latitude
+    double* Sm = lds;  // [L][C]
+    for (int idx = threadIdx.x; idx < L * C; idx += blockDim.x) {
+        const int d = idx / C, c = idx - d * C;
+        Sm[idx] = spec[((long long)((c_off + c) >> 1) * ns + so + d) * 2 + ((c_off + c) & 1)];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4;
-    const bool lat_ok = jrow < H;
-    for (int c0 = 0; c0 < C; c0 += 16) {
-        const int col = c0 + (lane & 15);
-        const bool col_ok = col < C;
-        const int b = col >> 1, ri = col & 1;
-        v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int cnt = (L - e + 1) / 2;  // degrees n = m + e + 2 i < m + L
-            for (int i0 = 0; i0 < cnt; i0 += 4) {
+    const int cnt0 = (L + 1) / 2, cnt1 = L / 2;  // degrees of each parity
+    for (int t = wk.t0 + wave; t < wk.t1; t += 4) {
+        const int j0 = t * 16;
+        const int jrow = j0 + (lane & 15);  // A row = latitude
+        const bool lat_ok = jrow < H;
+        for (int c0 = 0; c0 < C; c0 += 32) {
+            const int col0 = c0 + (lane & 15), col1 = col0 + 16;
+            const bool ok0 = col0 < C, ok1 = col1 < C;
+            v4d acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
+                             {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
+            for (int i0 = 0; i0 < cnt0; i0 += 4) {
                 const int i = i0 + kq;
-                double a = 0.0, bv = 0.0;
-                if (i < cnt) {
-                    const int n = m + e + 2 * i;
-                    if (lat_ok) a = plm[(so + (n - m)) * H + jrow];
-                    if (col_ok) bv = spec[((long long)b * ns + so + (n - m)) * 2 + ri];
-                }
-                acc[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[e], 0, 0, 0);
-            }
-        }
-        if (col_ok) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = tl.i0 + 4 * r + kq;
-                if (j < H) {
-                    Fw[((long long)m * nlat + j) * C + col] = acc[0][r] + acc[1][r];
-                    Fw[((long long)m * nlat + (nlat - 1 - j)) * C + col] = acc[0][r] - acc[1][r];
+                for (int e = 0; e < 2; ++e) {
+                    const bool iok = i < (e ? cnt1 : cnt0);
+                    const int d = e + 2 * i;
+                    const double a = (iok && lat_ok) ? plm[(so + d) * H + jrow] : 0.0;
+                    const double b0 = (iok && ok0) ? Sm[d * C + col0] : 0.0;
+                    const double b1 = (iok && ok1) ? Sm[d * C + col1] : 0.0;
+                    acc[e][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[e][0], 0, 0, 0);
+                    acc[e][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[e][1], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int col = h ? col1 : col0;
+                if (!(h ? ok1 : ok0)) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = j0 + 4 * r + kq;
+                    if (j < H) {
+                        Fw[((long long)m * nlat + j) * Cs + c_off + col] = acc[0][h][r] + acc[1][h][r];
+                        Fw[((long long)m * nlat + (nlat - 1 - j)) * Cs + c_off + col] = acc[0][h][r] - acc[1][h][r];
+                    }
                 }
             }
         }
@@ -222,17 +286,15 @@ int sh_setup(rexi_plan* pl) {
         const long double a = -2 * pi * k / nlon;
         tw[k] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    // tiles: forward (m, parity, 16 degrees); inverse (m, 16 latitudes)
-    std::vector<LegTile> tf, ti;
+    // work: runs of at most 8 tiles of one order (a workgroup of four waves)
+    std::vector<LegWork> tf, ti;
     for (int m = 0; m <= T; ++m) {
         const int L = T + 1 - m;
-        for (int e = 0; e < 2; ++e) {
-            const int cnt = (L - e + 1) / 2;
-            for (int i0 = 0; i0 < cnt; i0 += 16) tf.push_back(LegTile{m, e, i0, 0});
-        }
-        for (int j0 = 0; j0 < pl->nhalf; j0 += 16) ti.push_back(LegTile{m, 0, j0, 0});
+        const int nt = ((L + 1) / 2 + 15) / 16 + (L / 2 + 15) / 16;
+        for (int t0 = 0; t0 < nt; t0 += 8) tf.push_back(LegWork{m, t0, std::min(nt, t0 + 8), 0});
+        const int nl = (pl->nhalf + 15) / 16;
+        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), 0});
     }
-    // sort forward tiles so that the longest orders go first (roughly even waves)
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes ? bytes : 1);
         if (e != hipSuccess) return fail(REXI_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
@@ -242,14 +304,14 @@ int sh_setup(rexi_plan* pl) {
     if (!rc) rc = alloc((void**)&pl->d_wts, wn.size() * sizeof(double));
     if (!rc) rc = alloc((void**)&pl->d_twiddle, tw.size() * sizeof(double2));
     if (!rc) rc = alloc((void**)&pl->d_four, (size_t)(T + 1) * nlat * 2 * pl->prm.max_fields * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_tiles_f, tf.size() * sizeof(LegTile));
-    if (!rc) rc = alloc((void**)&pl->d_tiles_i, ti.size() * sizeof(LegTile));
+    if (!rc) rc = alloc((void**)&pl->d_tiles_f, tf.size() * sizeof(LegWork));
+    if (!rc) rc = alloc((void**)&pl->d_tiles_i, ti.size() * sizeof(LegWork));
     if (rc) return rc;
     REXI_HIP(hipMemcpy(pl->d_plm, plm.data(), plm.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_wts, wn.data(), wn.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
-    REXI_HIP(hipMemcpy(pl->d_tiles_f, tf.data(), tf.size() * sizeof(LegTile), hipMemcpyHostToDevice));
-    REXI_HIP(hipMemcpy(pl->d_tiles_i, ti.data(), ti.size() * sizeof(LegTile), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_tiles_f, tf.data(), tf.size() * sizeof(LegWork), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_tiles_i, ti.data(), ti.size() * sizeof(LegWork), hipMemcpyHostToDevice));
     pl->ntiles_f = (int)tf.size();
     pl->ntiles_i = (int)ti.size();
     return REXI_OK;
@@ -287,15 +349,28 @@ int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStr
                            pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);
         REXI_HIP(hipGetLastError());
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_FWD, s));
-        hipLaunchKernelGGL(k_legendre_forward, dim3(pl->ntiles_f), dim3(64), 0, s, (const LegTile*)pl->d_tiles_f,
-                           pl->d_plm, pl->d_wts, pl->d_four, (double*)out, pl->T, pl->nlat, pl->nhalf, C);
-        REXI_HIP(hipGetLastError());
+        // column chunks whose E/O blocks fit 64 KB of LDS
+        const int cc = std::max(2, std::min(C, (int)(kLdsBytes / (2 * sizeof(double) * pl->nhalf)) & ~1));
+        for (int c0 = 0; c0 < C; c0 += cc) {
+            const int w = std::min(cc, C - c0);
+            const size_t lf = sizeof(double) * 2 * (size_t)pl->nhalf * w;
+            hipLaunchKernelGGL(k_legendre_forward, dim3(pl->ntiles_f), dim3(256), lf, s,
+                               (const LegWork*)pl->d_tiles_f, pl->d_plm, pl->d_wts, pl->d_four, (double*)out,
+                               pl->T, pl->nlat, pl->nhalf, C, c0, w);
+            REXI_HIP(hipGetLastError());
+        }
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_FWD, s));
     } else {
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_INV, s));
-        hipLaunchKernelGGL(k_legendre_inverse, dim3(pl->ntiles_i), dim3(64), 0, s, (const LegTile*)pl->d_tiles_i,
-                           pl->d_plm, (const double*)in, pl->d_four, pl->T, pl->nlat, pl->nhalf, C);
-        REXI_HIP(hipGetLastError());
+        const int cc = std::max(2, std::min(C, (int)(kLdsBytes / (sizeof(double) * (pl->T + 1))) & ~1));
+        for (int c0 = 0; c0 < C; c0 += cc) {
+            const int w = std::min(cc, C - c0);
+            const size_t li = sizeof(double) * (size_t)(pl->T + 1) * w;
+            hipLaunchKernelGGL(k_legendre_inverse, dim3(pl->ntiles_i), dim3(256), li, s,
+                               (const LegWork*)pl->d_tiles_i, pl->d_plm, (const double*)in, pl->d_four, pl->T,
+                               pl->nlat, pl->nhalf, C, c0, w);
+            REXI_HIP(hipGetLastError());
+        }
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_INV, s));
         hipLaunchKernelGGL(k_fft_inverse, dim3(B * pl->nlat), dim3(256), lds, s, pl->d_four, (double*)out,
                            pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);

@@ -54,6 +54,7 @@ def load_library():
         "rexi_plan_autotune": [P, c_int, P, POINTER(c_int)],
         "rexi_plan_set_schedule": [P, c_int, c_int, POINTER(c_int)],
         "rexi_plan_set_timing": [P, c_int],
+        "rexi_plan_set_graphs": [P, c_int],
         "rexi_plan_kernel_time": [P, c_int, POINTER(c_double), POINTER(c_longlong)],
     }
     for name, args in sigs.items():
@@ -205,6 +206,9 @@ class Plan:
         _check(self._lib.rexi_plan_set_schedule(self._h, S, index, None), "rexi_plan_set_schedule")
 
     KERNEL_SOLVE, KERNEL_LEGENDRE_FWD, KERNEL_LEGENDRE_INV = 0, 1, 2
+
+    def set_graphs(self, enable: bool):
+        _check(self._lib.rexi_plan_set_graphs(self._h, int(enable)), "rexi_plan_set_graphs")
 
     def set_timing(self, enable: bool):
         _check(self._lib.rexi_plan_set_timing(self._h, int(enable)), "rexi_plan_set_timing")
