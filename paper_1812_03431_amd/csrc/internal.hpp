@@ -80,7 +80,7 @@ struct Group {
 // elements-per-lane class SE and the cross-lane move kind.
 struct Launch {
     int SE;
-    bool dpp;
+    int kind;  // cross-lane moves: 0 ds_bpermute, 1 DPP within 16-lane rows, 2 DPP over row pairs
     int item0, nitems;
     int pmax;  // largest lane group of the launch (sizes its LDS)
 };

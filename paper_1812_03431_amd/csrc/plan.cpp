@@ -15,7 +15,7 @@
 
 namespace rexi {
 
-bool solve_variant_supported(int SE, bool dpp);
+bool solve_variant_supported(int SE, int kind, bool per_term);
 int solve_waves_per_item();
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
                         hipStream_t s);
@@ -128,20 +128,22 @@ std::vector<MInfo> chain_layout(int T) {
     return mi;
 }
 
-// Elements-per-lane class of a chain of L elements under a policy:
-//   0 "mixed": 8 (L <= 128), 12 (<= 192), 16 (<= 256), then 16 with bpermute
-//   1 "8/16" : 8 (L <= 128), 16 (<= 256), then 16 with bpermute
-//   2 "16"   : 16 (L <= 256), then 16 with bpermute
-//   3 "8"    : 8 (L <= 128), then 8 with bpermute (L <= 512), then 16 with bpermute
-//   4 "4"    : 4 with bpermute (L <= 256), then 8 / 16 with bpermute
-// Groups of at most 16 lanes move data with DPP row shifts.
-void tile_class(int policy, int L, int& SE, bool& dpp) {
-    dpp = true;
+// Elements-per-lane class SE and cross-lane move kind of a chain of L
+// elements under a policy.  Kinds: 0 ds_bpermute (groups up to 64 lanes),
+// 1 DPP row shifts (groups inside one 16-lane row), 2 DPP over a pair of rows
+// (groups of exactly 32 lanes).
+//   0 "8":       8 (L <= 128, rows), 8 (L <= 256, row pairs)
+//   1 "8/16":    8 (L <= 128), 16 (<= 256), rows
+//   2 "16":      16 (L <= 256), rows
+//   3 "8/12/16": 8 (L <= 128), 12 (<= 192), 16 (<= 256), rows
+//   4 "4/8":     4 (L <= 64, rows), 4 (L <= 128, row pairs), 8 (L <= 256, row pairs)
+// Beyond 256 elements every policy uses 16 with ds_bpermute (L <= 1024).
+void tile_class(int policy, int L, int& SE, int& kind) {
+    kind = 1;
     switch (policy) {
         case 0:
             if (L <= 128) { SE = 8; return; }
-            if (L <= 192) { SE = 12; return; }
-            if (L <= 256) { SE = 16; return; }
+            if (L <= 256) { SE = 8; kind = 2; return; }
             break;
         case 1:
             if (L <= 128) { SE = 8; return; }
@@ -152,20 +154,20 @@ void tile_class(int policy, int L, int& SE, bool& dpp) {
             break;
         case 3:
             if (L <= 128) { SE = 8; return; }
-            dpp = false;
-            if (L <= 512) { SE = 8; return; }
+            if (L <= 192) { SE = 12; return; }
+            if (L <= 256) { SE = 16; return; }
             break;
         default:
-            dpp = false;
-            if (L <= 256) { SE = 4; return; }
-            if (L <= 512) { SE = 8; return; }
+            if (L <= 64) { SE = 4; return; }
+            if (L <= 128) { SE = 4; kind = 2; return; }
+            if (L <= 256) { SE = 8; kind = 2; return; }
             break;
     }
-    dpp = false;
+    kind = 0;
     SE = 16;
 }
 
-const char* kPolicyName[] = {"mixed", "8/16", "16", "8", "4"};
+const char* kPolicyName[] = {"8", "8/16", "16", "8/12/16", "4/8"};
 constexpr int kPolicies = 5;
 
 // Work split of one candidate schedule.  Items are (m, chain, state, pole
@@ -181,29 +183,29 @@ int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, boo
     out.minfo = chain_layout(T);
     struct Unit { int m, p, tile; double cost; int iters; int G; int cls; };
     std::vector<Unit> units;
-    std::vector<std::pair<int, bool>> classes;
+    std::vector<std::pair<int, int>> classes;
     double total = 0;
     for (int m = 0; m <= T; ++m) {
         MInfo& mi = out.minfo[m];
-        int SE;
-        bool dpp;
-        tile_class(policy, mi.L, SE, dpp);
-        if (!solve_variant_supported(SE, dpp)) return fail(REXI_EUNSUPPORTED, "tile class not compiled");
+        int SE, kind;
+        tile_class(policy, mi.L, SE, kind);
+        if (!solve_variant_supported(SE, kind, per_term)) return fail(REXI_EUNSUPPORTED, "tile class not compiled");
         int P = 1;
         while (P * SE < mi.L) P *= 2;
-        if (P > (dpp ? 16 : 64)) return fail(REXI_EUNSUPPORTED, "chain too long for this tiling");
+        if (kind == 1 ? P > 16 : kind == 2 ? P != 32 : P > 64)
+            return fail(REXI_EUNSUPPORTED, "chain length does not fit this tiling");
         mi.P = P;
         mi.s = SE;
         out.SM = std::max(out.SM, SE);
         int cls = -1;
         for (int c = 0; c < (int)classes.size(); ++c)
-            if (classes[c].first == SE && classes[c].second == dpp) cls = c;
-        if (cls < 0) { cls = (int)classes.size(); classes.push_back({SE, dpp}); }
+            if (classes[c].first == SE && classes[c].second == kind) cls = c;
+        if (cls < 0) { cls = (int)classes.size(); classes.push_back({SE, kind}); }
         const int G = 64 / P * (per_term ? 1 : solve_waves_per_item());  // poles per workgroup iteration
         int lg = 0;
         while ((1 << lg) < P) ++lg;
         const double occ = SE <= 8 ? 2.0 : 1.0;
-        const double it_cost = (SE * 100.0 + lg * (dpp ? 90.0 : 160.0) + 60.0) / occ;
+        const double it_cost = (SE * 100.0 + lg * (kind == 0 ? 160.0 : kind == 2 ? 100.0 : 90.0) + 60.0) / occ;
         const int iters = (N + G - 1) / G;
         for (int p = 0; p < 2; ++p)
             for (int t = 0; t < S; ++t) {
@@ -304,7 +306,7 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
                     c.push_back(sc);
                 }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
-        pl->chosen[S] = 2;  // until autotuned: "mixed", ~4096 items
+        pl->chosen[S] = 2;  // until autotuned: policy "8", ~4096 items
     }
     *out = &c;
     return REXI_OK;
@@ -655,7 +657,7 @@ int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* s
         if ((int)plan->per_term.size() <= S) plan->per_term.resize(S + 1);
         Schedule& sc = plan->per_term[S];
         if (sc.items.empty()) {
-            rc = build_schedule(plan, S, 3, 0, true, sc);  // 8 elements per lane, one wave per chain
+            rc = build_schedule(plan, S, 0, 0, true, sc);  // 8 elements per lane, one wave per chain
             if (rc) { free_schedule(sc); sc = Schedule(); return rc; }
         }
         if (sc.part_size > plan->acc_capacity) {

@@ -106,7 +106,7 @@ struct SolveArgs {
 };
 
 constexpr int kWaves = 4;   // waves per workgroup; they share one item's staged data
-constexpr int kStage = 12;  // doubles staged per chain position
+constexpr int kStage = 8;   // doubles staged per chain position
 
 __device__ __forceinline__ cd crcp_newton(cd a) {
     // 1/(x + i y) = (x - i y)/(x^2 + y^2); the real reciprocal by v_rcp_f64 and
@@ -125,49 +125,98 @@ __device__ __forceinline__ cd cfma_cj(cd acc, cd w, cd x) {
     return cd{fma(w.r, x.r, fma(-w.i, x.i, acc.r)), fma(-w.r, x.i, fma(-w.i, x.r, acc.i))};
 }
 
-// Cross-lane moves inside a chain's lane group.  With DPP (groups of at most 16
-// lanes, aligned to the 16-lane rows) they are row shifts on the VALU:
-// row_shr:D gives lane i the value of lane i-D, row_shl:D that of lane i+D
-// (zero where the source lies outside the row).  Otherwise ds_bpermute.
+// Cross-lane moves of the interface solve.  The P lanes of one chain form a
+// group; "lo" receives the value of chain lane l - D, "hi" that of l + D
+// (finite but meaningless where that lane lies outside the group: the callers
+// multiply it by zero there).
+//   kind 0: group = lanes [g P, g P + P), any P <= 64, ds_bpermute.
+//   kind 1: the same with P <= 16, so a group lies inside one 16-lane row and
+//           moves are DPP row shifts (row_shr:D gives lane i the value of lane
+//           i - D, row_shl:D that of lane i + D, zero outside the row).
+//   kind 2: P = 32 over the row pair (2g, 2g + 1) with chain lane l = 2 j + r
+//           for row-local lane j and row r of the pair.  Strides D >= 2 stay
+//           inside the row (a shift by D/2); stride 1 crosses rows:
+//           v_permlane16_swap hands each row its partner row's value, and a
+//           one-lane row shift applied to one row of the pair completes it.
+constexpr int kMoveBperm = 0, kMoveRow = 1, kMovePair = 2;
+
 template <int CTRL>
-__device__ __forceinline__ double dpp_move(double x) {
+__device__ __forceinline__ double dpp_zero(double x) {
     const long long v = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-template <bool DPP, int D>
+// kind 2, stride 1, on one 32-bit word.  After the swap, s[0] holds in the
+// odd row of each pair the even row's value and s[1] in the even row the odd
+// row's value (same row-local lane).  Even rows (r = 0, l = 2j) take l - 1 =
+// (j - 1, odd row) and keep l + 1 = (j, odd row); odd rows (l = 2j + 1) keep
+// l - 1 = (j, even row) and take l + 1 = (j + 1, even row).
+__device__ __forceinline__ void pair_step(int w, int& lo, int& hi) {
+    const auto s = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+    lo = __builtin_amdgcn_update_dpp((int)s[0], (int)s[1], 0x111, 0x5, 0xF, false);  // row_shr:1, even rows
+    hi = __builtin_amdgcn_update_dpp((int)s[1], (int)s[0], 0x101, 0xA, 0xF, false);  // row_shl:1, odd rows
+}
+__device__ __forceinline__ void pair_step(double x, double& lo, double& hi) {
+    const long long v = __double_as_longlong(x);
+    int l0, h0, l1, h1;
+    pair_step((int)(unsigned)v, l0, h0);
+    pair_step((int)(v >> 32), l1, h1);
+    lo = __longlong_as_double(((long long)l1 << 32) | (long long)(unsigned)l0);
+    hi = __longlong_as_double(((long long)h1 << 32) | (long long)(unsigned)h0);
+}
+
+template <int KIND, int D>
 struct Mover {
-    __device__ static __forceinline__ cd below(cd x, int lane) {  // value of lane - D
-        if constexpr (DPP) return cd{dpp_move<0x110 + D>(x.r), dpp_move<0x110 + D>(x.i)};
-        else return shfl(x, (lane - D) & 63);
+    __device__ static __forceinline__ void both(cd x, int lane, cd& lo, cd& hi) {
+        if constexpr (KIND == kMoveBperm) {
+            lo = shfl(x, (lane - D) & 63);
+            hi = shfl(x, (lane + D) & 63);
+        } else if constexpr (KIND == kMoveRow) {
+            lo = cd{dpp_zero<0x110 + D>(x.r), dpp_zero<0x110 + D>(x.i)};
+            hi = cd{dpp_zero<0x100 + D>(x.r), dpp_zero<0x100 + D>(x.i)};
+        } else if constexpr (D == 1) {
+            pair_step(x.r, lo.r, hi.r);
+            pair_step(x.i, lo.i, hi.i);
+        } else {
+            lo = cd{dpp_zero<0x110 + D / 2>(x.r), dpp_zero<0x110 + D / 2>(x.i)};
+            hi = cd{dpp_zero<0x100 + D / 2>(x.r), dpp_zero<0x100 + D / 2>(x.i)};
+        }
     }
-    __device__ static __forceinline__ cd above(cd x, int lane) {  // value of lane + D
-        if constexpr (DPP) return cd{dpp_move<0x100 + D>(x.r), dpp_move<0x100 + D>(x.i)};
-        else return shfl(x, (lane + D) & 63);
+    __device__ static __forceinline__ cd below(cd x, int lane) {
+        cd lo, hi;
+        both(x, lane, lo, hi);
+        return lo;
+    }
+    __device__ static __forceinline__ cd above(cd x, int lane) {
+        cd lo, hi;
+        both(x, lane, lo, hi);
+        return hi;
     }
 };
 
 // One cyclic-reduction level with stride D: matrix row (A, B, C) and two
 // right-hand sides (Du, Dw).
-template <bool DPP, int D>
+template <int KIND, int D>
 __device__ __forceinline__ void pcr_level(cd& Ac, cd& Bc, cd& Cc, cd& Du, cd& Dw, int l, int P, int lane) {
-    typedef Mover<DPP, D> Mv;
-    const cd ib = crcp_newton(Bc);
-    const cd AL = Mv::below(Ac, lane), CL = Mv::below(Cc, lane), IL = Mv::below(ib, lane);
-    const cd DuL = Mv::below(Du, lane), DwL = Mv::below(Dw, lane);
-    const cd AR = Mv::above(Ac, lane), CR = Mv::above(Cc, lane), IR = Mv::above(ib, lane);
-    const cd DuR = Mv::above(Du, lane), DwR = Mv::above(Dw, lane);
-    // neighbours outside the chain's group: multipliers are zero (every lane
-    // holds finite values, so the products below vanish)
-    const cd k1 = (l >= D) ? cmul(Ac, IL) : mk(0, 0);
-    const cd k2 = (l + D < P) ? cmul(Cc, IR) : mk(0, 0);
-    Bc = cfms(cfms(Bc, k1, CL), k2, AR);
-    Du = cfms(cfms(Du, k1, DuL), k2, DuR);
-    Dw = cfms(cfms(Dw, k1, DwL), k2, DwR);
-    Ac = cneg(cmul(k1, AL));
-    Cc = cneg(cmul(k2, CR));
+    typedef Mover<KIND, D> Mv;
+    // neighbours outside the chain's group: multipliers are zero.  Each moved
+    // value is consumed before the next move (keeps few values live).
+    cd lo, hi;
+    Mv::both(crcp_newton(Bc), lane, lo, hi);
+    const cd k1 = (l >= D) ? cmul(Ac, lo) : mk(0, 0);
+    const cd k2 = (l + D < P) ? cmul(Cc, hi) : mk(0, 0);
+    Mv::both(Cc, lane, lo, hi);
+    Bc = cfms(Bc, k1, lo);
+    Cc = cneg(cmul(k2, hi));
+    Mv::both(Ac, lane, lo, hi);
+    Bc = cfms(Bc, k2, hi);
+    Ac = cneg(cmul(k1, lo));
+    Mv::both(Du, lane, lo, hi);
+    Du = cfms(cfms(Du, k1, lo), k2, hi);
+    Mv::both(Dw, lane, lo, hi);
+    Dw = cfms(cfms(Dw, k1, lo), k2, hi);
 }
 
 // One work item: chain p of order m, one state, a pole range.  SE elements per
@@ -183,54 +232,65 @@ __device__ __forceinline__ void pcr_level(cd& Ac, cd& Bc, cd& Cc, cd& Du, cd& Dw
 // interface rows (one per lane) are solved by cyclic reduction across the
 // chain's P lanes, matrix and both right-hand sides in the same levels, and a
 // reverse sweep recovers the interior with both interface values.
-template <int SE, int PH, bool ACCUM, bool DPP, int W>
+//
+// Mirrored right-hand side: with jv = -(-1)^n the J sign of vorticity and
+// divergence, the staged chain data v gives conj(J v) = jv conj(v) on the
+// chain and -jv conj(r^Phi) on Phi.  Since SE is even, jv = j0 (-1)^t with one
+// sign j0 per item; the solve is linear, so j0 is dropped from the right-hand
+// side and cancels against the same factor of J on the output.  What remains
+// is (-1)^t on input and output.
+template <int SE, int PH, bool ACCUM, int KIND, int W>
 __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, const MInfo& mi, double* sm) {
+    static_assert(SE % 2 == 0, "elements per lane must be even");
     constexpr int NI = SE - 1;  // interior elements 0 .. SE-2; interface SE-1
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int P = mi.P, L = mi.L, n0 = mi.n0, m = it.m, p = it.p;
+    const int P = (KIND == kMovePair) ? 32 : mi.P;
+    const int L = mi.L, n0 = mi.n0, m = it.m, p = it.p;
     const int G = 64 / P;
-    const int g = lane / P, l = lane - g * P;
+    int g, l;
+    if constexpr (KIND == kMovePair) {
+        g = lane >> 5;
+        l = 2 * (lane & 15) + ((lane >> 4) & 1);
+    } else {
+        g = lane / P;
+        l = lane - g * P;
+    }
+    // LDS slot of chain lane l: its lane within the group (kind 2: j + 16 r);
+    // slots per chunk fixed at compile time so that every LDS offset below is
+    // an immediate
+    const int slot = (KIND == kMovePair) ? (lane & 31) : l;
+    constexpr int PS = (KIND == kMoveRow) ? 16 : (KIND == kMovePair) ? 32 : 64;
     const int st = it.tile;
     const int npos = P * SE;
 
-    // ---- stage the item's constants and right-hand sides in LDS, [t][l] order:
-    // (th, om, cl, cr, rv, rp, rvw, rpw) with rvw = J conj(rv), rpw = J conj(rp)
-    double* c = sm;
+    // ---- stage the item's constants and right-hand sides in LDS as four
+    // double2 chunks per position, [t][chunk][slot], so that the lanes of a row
+    // read consecutive 16-byte words: (th, om), (c_left, c_right), r_var, r_Phi
+    double2* c = reinterpret_cast<double2*>(sm);
     for (int j = tid; j < npos; j += blockDim.x) {
         const int l2 = j / SE, t2 = j - l2 * SE;
+        const int s2 = (KIND == kMovePair) ? ((l2 >> 1) + 16 * (l2 & 1)) : l2;
         const int n = n0 + j;
-        double v[kStage] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double2 v0 = make_double2(0.0, 0.0), v1 = v0, v2 = v0, v3 = v0;
         if (j < L) {
             const long long i = mi.spec_off + (n - m);
-            v[0] = A.th[i];
-            v[1] = A.om[i];
-            v[2] = (j > 0) ? A.cc[i] : 0.0;
-            v[3] = (n < A.T) ? A.cc[i + 1] : 0.0;
-            const double2 rv = A.ch_var[st * A.var_stride + mi.slot_base + (long long)p * L + j];
-            const double jv = (n & 1) ? 1.0 : -1.0;  // J on vorticity / divergence: -(-1)^n
-            v[4] = rv.x;
-            v[5] = rv.y;
-            v[8] = jv * rv.x;
-            v[9] = -jv * rv.y;
-            if ((n + p) & 1) {
-                const double2 rp = A.ch_phi[st * A.nspec + i];
-                v[6] = rp.x;
-                v[7] = rp.y;
-                v[10] = jv * rp.x;
-                v[11] = -jv * rp.y;
-            }
+            v0 = make_double2(A.th[i], A.om[i]);
+            v1 = make_double2((j > 0) ? A.cc[i] : 0.0, (n < A.T) ? A.cc[i + 1] : 0.0);
+            v2 = A.ch_var[st * A.var_stride + mi.slot_base + (long long)p * L + j];
+            if ((n + p) & 1) v3 = A.ch_phi[st * A.nspec + i];
         }
-        double* o = c + (size_t)(t2 * P + l2) * kStage;
-#pragma unroll
-        for (int r = 0; r < kStage; ++r) o[r] = v[r];
+        double2* o = c + (size_t)(t2 * 4) * PS + s2;
+        o[0] = v0;
+        o[PS] = v1;
+        o[2 * PS] = v2;
+        o[3 * PS] = v3;
     }
     __syncthreads();
 
     bool vd[SE];
 #pragma unroll
     for (int t = 0; t < SE; ++t) vd[t] = (l * SE + t) < L;
-    const double jb = (n0 & 1) ? 1.0 : -1.0;  // J sign of the chain variable at even t
 
     cd av[SE], ap[SE];
 #pragma unroll
@@ -238,41 +298,94 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
 
     const int stride = W * G;
 
+    // staged data of position t of this lane
+    struct Pos {
+        double2 c0, c1, rv, rp;
+    };
+    auto fetch = [&](int t) {
+        const double2* o = c + (size_t)(t * 4) * PS + slot;
+        Pos x;
+        x.c0 = o[0];
+        x.c1 = o[PS];
+        x.rv = o[2 * PS];
+        x.rp = ((PH + t) & 1) ? o[3 * PS] : make_double2(0.0, 0.0);
+        return x;
+    };
+    // Latency hiding where registers allow (row groups): the pole and its
+    // reciprocal are fetched one iteration ahead, the staged data of position
+    // t + 1 before the work on t, and scheduling barriers keep these reads
+    // where they are.  The row-pair kind has no registers to spare for it.
+    constexpr bool kAhead = (KIND == kMoveRow);
+    cd al_n = mk(0, 0), ai_n = mk(0, 0);
+    if constexpr (kAhead) {
+        const int k = it.k0 + wave * G + g;
+        const PoleData& pn = A.poles[k < it.k1 ? k : it.k0];
+        al_n = cd{pn.al.x, pn.al.y};
+        ai_n = cd{pn.ai.x, pn.ai.y};
+    }
+
     for (int kb = it.k0; kb < it.k1; kb += stride) {
         if (kb + wave * G >= it.k1) continue;  // this wave has no pole left (uniform)
         const int k = kb + wave * G + g;
         const bool act = k < it.k1;
         const PoleData& pd = A.poles[act ? k : it.k0];
-        const cd al = cd{pd.al.x, pd.al.y}, ai = cd{pd.ai.x, pd.ai.y};
+        cd al, ai;
+        if constexpr (kAhead) {
+            al = al_n;
+            ai = ai_n;
+            const int kn = k + stride;
+            const PoleData& pn = A.poles[kn < it.k1 ? kn : it.k0];
+            al_n = cd{pn.al.x, pn.al.y};
+            ai_n = cd{pn.ai.x, pn.ai.y};
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            al = cd{pd.al.x, pd.al.y};
+            ai = cd{pd.ai.x, pd.ai.y};
+        }
 
         cd e[NI], gv[NI], Gu[NI], Gw[NI];
         cd pi = mk(1, 0), v0 = mk(0, 0), w0 = mk(0, 0), g0u = mk(0, 0), g0w = mk(0, 0);
         cd qprev = mk(0, 0);
         double cbprev = 0.0;
-        // element data of position t of this lane: diagonal b, couplings, RHS
-        auto element = [&](int t, cd& b, double& ca, double& cb, cd& du, cd& dw) {
-            const double* o = c + (size_t)(t * P + l) * kStage;
-            const double sg = ((PH + t) & 1) ? 1.0 : -1.0;
-            ca = sg * o[2];
-            cb = sg * o[3];
-            const cd rv = cd{o[4], o[5]}, rvw = cd{o[8], o[9]};
+        // element of position t: diagonal b, couplings, and both right-hand
+        // sides (the mirrored one as described above)
+        auto element = [&](int t, const Pos& x, cd& b, double& ca, double& cb, cd& du, cd& dw) {
+            const double sg = ((PH + t) & 1) ? 1.0 : -1.0;  // divergence rows +, vorticity rows -
+            const double ts = (t & 1) ? -1.0 : 1.0;         // (-1)^t
+            ca = sg * x.c1.x;
+            cb = sg * x.c1.y;
             if ((PH + t) & 1) {
-                const double om = o[1];
+                // divergence element, Phi eliminated: diagonal alpha + i th + om^2/alpha,
+                // right-hand side r_div - (om/alpha) r_Phi
+                const double om = x.c0.y;
                 const cd f = cscale(ai, om);
-                b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, o[0]));
-                du = cfms(rv, f, cd{o[6], o[7]});
-                dw = cfma(rvw, f, cd{o[10], o[11]});
+                b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, x.c0.x));
+                du = cfms(cd{x.rv.x, x.rv.y}, f, cd{x.rp.x, x.rp.y});
+                const double wr = fma(f.r, x.rp.x, fma(f.i, x.rp.y, x.rv.x));
+                const double wi = fma(f.i, x.rp.x, fma(-f.r, x.rp.y, -x.rv.y));
+                dw = cd{ts * wr, ts * wi};
             } else {
-                b = mk(al.r, al.i + o[0]);
-                du = rv;
-                dw = rvw;
+                b = mk(al.r, al.i + x.c0.x);
+                du = cd{x.rv.x, x.rv.y};
+                dw = cd{ts * x.rv.x, -ts * x.rv.y};
             }
         };
+        // forward sweep (with kAhead the next position's data is read before
+        // this one's work)
+        Pos cur;
+        if constexpr (kAhead) cur = fetch(0);
 #pragma unroll
         for (int t = 0; t < NI; ++t) {
+            Pos nxt;
+            if constexpr (kAhead) {
+                nxt = fetch(t + 1);
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+                cur = fetch(t);
+            }
             cd b, du, dw;
             double ca, cb;
-            element(t, b, ca, cb, du, dw);
+            element(t, cur, b, ca, cb, du, dw);
             if (t > 0) b = csubs(b, ca * cbprev, qprev);
             const cd q = crcp_newton(b);
             e[t] = cscale(q, cb);
@@ -292,14 +405,21 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
             pi = cneg(cmul(pi, e[t]));
             qprev = q;
             cbprev = cb;
+            if constexpr (kAhead) cur = nxt;
         }
+
+        // this pole's weights: read here, used after the interface solve
+        cd wx = cd{pd.wx.x, pd.wx.y}, wxa = cd{pd.wxa.x, pd.wxa.y};
+        cd wyE = cd{pd.wy.x, pd.wy.y}, wyaE = cd{pd.wya.x, pd.wya.y};
+        if constexpr (kAhead) __builtin_amdgcn_sched_barrier(0);
 
         // interface row -> tridiagonal system over the P lanes of the chain;
         // the right neighbour's values enter with cI, which is zero at a chain end
         cd bI, dIu, dIw;
         double aI, cI;
-        element(SE - 1, bI, aI, cI, dIu, dIw);
-        typedef Mover<DPP, 1> M1;
+        if constexpr (!kAhead) cur = fetch(SE - 1);
+        element(SE - 1, cur, bI, aI, cI, dIu, dIw);
+        typedef Mover<KIND, 1> M1;
         const cd vN = M1::above(v0, lane), wN = M1::above(w0, lane);
         const cd guN = M1::above(g0u, lane), gwN = M1::above(g0w, lane);
         cd Ac = cneg(cscale(gv[NI - 1], aI));
@@ -309,23 +429,31 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         cd Dw = csubs(csubs(dIw, aI, Gw[NI - 1]), cI, gwN);
 
         // cyclic reduction over the lanes of the chain
-        if (1 < P) pcr_level<DPP, 1>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-        if (2 < P) pcr_level<DPP, 2>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-        if (4 < P) pcr_level<DPP, 4>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-        if (8 < P) pcr_level<DPP, 8>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-        if constexpr (!DPP) {
-            if (16 < P) pcr_level<DPP, 16>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            if (32 < P) pcr_level<DPP, 32>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+        if constexpr (KIND == kMovePair) {
+            pcr_level<KIND, 1>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            pcr_level<KIND, 2>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            pcr_level<KIND, 4>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            pcr_level<KIND, 8>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            pcr_level<KIND, 16>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+        } else {
+            if (1 < P) pcr_level<KIND, 1>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            if (2 < P) pcr_level<KIND, 2>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            if (4 < P) pcr_level<KIND, 4>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            if (8 < P) pcr_level<KIND, 8>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            if constexpr (KIND == kMoveBperm) {
+                if (16 < P) pcr_level<KIND, 16>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+                if (32 < P) pcr_level<KIND, 32>(Ac, Bc, Cc, Du, Dw, l, P, lane);
+            }
         }
         const cd iB = crcp_newton(Bc);
         const cd Xu = cmul(Du, iB), Xw = cmul(Dw, iB);
         // the left neighbour's interface values (enter through gv, zero at a chain start)
         const cd XLu = M1::below(Xu, lane), XLw = M1::below(Xw, lane);
 
-        // reverse sweep with both interface values; weighted sums.  The J sign of
-        // the mirrored solve is folded into its weights per element parity.
-        cd wx = cd{pd.wx.x, pd.wx.y}, wxa = cd{pd.wxa.x, pd.wxa.y};
-        cd wyE = cscale(cd{pd.wy.x, pd.wy.y}, jb), wyaE = cscale(cd{pd.wya.x, pd.wya.y}, -jb);
+        // reverse sweep with both interface values; weighted sums.  The mirrored
+        // solution enters conjugated with (-1)^t on the chain variable and
+        // -(-1)^t on Phi.
+        wyaE = cneg(wyaE);
         if (!act) wx = wxa = wyE = wyaE = mk(0, 0);
         cd xu = Xu, xw = Xw;
 #pragma unroll
@@ -345,7 +473,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         }
     }
 
-    // sum the G groups of each wave (same positions) in a fixed tree order
+    // sum the G groups of each wave (same chain lanes) in a fixed tree order
     for (int off = 32; off >= P; off >>= 1) {
         const int src = (lane + off) & 63;
 #pragma unroll
@@ -356,7 +484,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     }
     // then the waves, in order, through LDS (reusing the staging area)
     __syncthreads();
-    double2* acc = reinterpret_cast<double2*>(sm);  // [2][SE][P]
+    double2* acc = c;  // [2][SE][P]
     for (int wv = 0; wv < W; ++wv) {
         if (wave == wv && g == 0) {
 #pragma unroll
@@ -392,22 +520,25 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     }
 }
 
-template <int SE, bool ACCUM, bool DPP, int W>
+template <int SE, bool ACCUM, int KIND, int W>
 __device__ __forceinline__ void run_item(const SolveArgs& A, int idx, double* sm) {
     const Item it = A.items[idx];
     const MInfo mi = A.minfo[it.m];
-    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, DPP, W>(A, it, mi, sm);
-    else solve_item<SE, 0, ACCUM, DPP, W>(A, it, mi, sm);
+    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, KIND, W>(A, it, mi, sm);
+    else solve_item<SE, 0, ACCUM, KIND, W>(A, it, mi, sm);
 }
 
 // One workgroup per item (counter == null), or persistent: a grid of resident
 // workgroups takes items [item0, item0 + nitems) from an atomic counter that
 // starts at zero, until none is left (every workgroup then leaves the loop).
-template <int SE, bool ACCUM, bool DPP, int W>
-__global__ void __launch_bounds__(64 * W) k_solve(const SolveArgs A, int item0, int nitems, int* counter) {
+// Tiles of up to 8 elements per lane are held to 256 registers (two waves per
+// SIMD); larger ones use the whole register file.
+template <int SE, bool ACCUM, int KIND, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(SE <= 8 ? 2 : 1)))
+k_solve(const SolveArgs A, int item0, int nitems, int* counter) {
     extern __shared__ double sm[];
     if (counter == nullptr) {
-        run_item<SE, ACCUM, DPP, W>(A, item0 + blockIdx.x, sm);
+        run_item<SE, ACCUM, KIND, W>(A, item0 + blockIdx.x, sm);
         return;
     }
     __shared__ int next;
@@ -417,7 +548,7 @@ __global__ void __launch_bounds__(64 * W) k_solve(const SolveArgs A, int item0, 
         const int i = next;
         __syncthreads();
         if (i < 0 || i >= nitems) break;
-        run_item<SE, ACCUM, DPP, W>(A, item0 + i, sm);
+        run_item<SE, ACCUM, KIND, W>(A, item0 + i, sm);
     }
 }
 
@@ -560,10 +691,12 @@ __global__ void k_zero(double2* p, long long n) {
 // LDS of one workgroup: the staged positions of the largest chain group.
 // The batched form runs kWaves waves per workgroup (sharing the staged data of
 // an item); the per-term form (ACC) one wave per chain.
-template <int SE, bool ACC, bool DPP>
+template <int SE, bool ACC, int KIND>
 hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, int* counter, hipStream_t s) {
     constexpr int W = ACC ? 1 : kWaves;
-    const size_t lds = sizeof(double) * kStage * (size_t)(pmax * SE);
+    constexpr int PS = (KIND == kMoveRow) ? 16 : (KIND == kMovePair) ? 32 : 64;  // LDS slots per chunk
+    (void)pmax;
+    const size_t lds = sizeof(double) * kStage * (size_t)(PS * SE);
     int grid = nitems;
     if (counter) {
         // resident workgroups of this kernel on the whole device
@@ -571,40 +704,51 @@ hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, i
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<SE, ACC, DPP, W>, 64 * W, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<SE, ACC, KIND, W>, 64 * W, lds);
         if (e != hipSuccess) return e;
         grid = std::max(1, std::min(nitems, std::max(1, per_cu) * ncu));
     }
-    hipLaunchKernelGGL((k_solve<SE, ACC, DPP, W>), dim3(grid), dim3(64 * W), lds, s, a, item0, nitems, counter);
+    hipLaunchKernelGGL((k_solve<SE, ACC, KIND, W>), dim3(grid), dim3(64 * W), lds, s, a, item0, nitems, counter);
     return hipGetLastError();
 }
+
+// Compiled tilings: (elements per lane, move kind).  The per-term form needs
+// only those of the default policy.
+constexpr int kVariants[][2] = {{4, kMoveRow}, {8, kMoveRow}, {12, kMoveRow}, {16, kMoveRow},
+                                {4, kMovePair}, {8, kMovePair}, {16, kMoveBperm}};
+constexpr int kPerTermVariants[][2] = {{8, kMoveRow}, {8, kMovePair}, {16, kMoveBperm}};
 
 template <bool ACC>
 hipError_t launch_solve(const Launch& L, const SolveArgs& a, int* counter, hipStream_t s) {
     if (L.nitems <= 0) return hipSuccess;
-    if (L.pmax > (L.dpp ? 16 : 64)) return hipErrorInvalidValue;
-    if (L.dpp) {
-        switch (L.SE) {
-            case 8: return launch_solve_t<8, ACC, true>(a, L.item0, L.nitems, L.pmax, counter, s);
-            case 12: return launch_solve_t<12, ACC, true>(a, L.item0, L.nitems, L.pmax, counter, s);
-            case 16: return launch_solve_t<16, ACC, true>(a, L.item0, L.nitems, L.pmax, counter, s);
-            default: return hipErrorInvalidValue;
-        }
+    const int pcap = L.kind == kMoveRow ? 16 : L.kind == kMovePair ? 32 : 64;
+    if (L.pmax > pcap) return hipErrorInvalidValue;
+#define REXI_CASE(SE_, K_) \
+    if (L.SE == SE_ && L.kind == K_) return launch_solve_t<SE_, ACC, K_>(a, L.item0, L.nitems, L.pmax, counter, s)
+    REXI_CASE(8, kMoveRow);
+    REXI_CASE(8, kMovePair);
+    REXI_CASE(16, kMoveBperm);
+    if constexpr (!ACC) {
+        REXI_CASE(4, kMoveRow);
+        REXI_CASE(12, kMoveRow);
+        REXI_CASE(16, kMoveRow);
+        REXI_CASE(4, kMovePair);
     }
-    switch (L.SE) {
-        case 4: return launch_solve_t<4, ACC, false>(a, L.item0, L.nitems, L.pmax, counter, s);
-        case 8: return launch_solve_t<8, ACC, false>(a, L.item0, L.nitems, L.pmax, counter, s);
-        case 16: return launch_solve_t<16, ACC, false>(a, L.item0, L.nitems, L.pmax, counter, s);
-        default: return hipErrorInvalidValue;
-    }
+#undef REXI_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-// Tilings compiled into the library: elements per lane, and whether the
-// lane group fits a 16-lane row (DPP moves) or needs ds_bpermute.
-bool solve_variant_supported(int SE, bool dpp) {
-    return dpp ? (SE == 8 || SE == 12 || SE == 16) : (SE == 4 || SE == 8 || SE == 16);
+bool solve_variant_supported(int SE, int kind, bool per_term) {
+    if (per_term) {
+        for (const auto& v : kPerTermVariants)
+            if (v[0] == SE && v[1] == kind) return true;
+        return false;
+    }
+    for (const auto& v : kVariants)
+        if (v[0] == SE && v[1] == kind) return true;
+    return false;
 }
 int solve_waves_per_item() { return kWaves; }
 

@@ -65,6 +65,30 @@ def test_step_ragged_and_partial_tiles(torch_dev, T, S, M, dt):
     assert_parity(got, want, what=f"T{T} S{S} per-term")
 
 
+@pytest.mark.parametrize("T,S,M,dt,orders", [
+    (160, 2, 32, 600.0, [0, 1, 31, 32, 33, 63, 95, 96, 97, 159, 160]),
+    (255, 1, 24, 300.0, [0, 1, 2, 64, 126, 127, 128, 191, 254, 255]),
+])
+def test_step_long_chains_every_schedule(torch_dev, T, S, M, dt, orders):
+    # chains of up to 255 elements: 32-lane groups over row pairs and the
+    # 12/16-element row tilings, for every policy, both directions
+    w = synth.Workload("long", T=T, nlat=0, nlon=0, dt=dt, M=M, states=S)
+    u0 = synth.random_state(T, S, 200 + T)
+    mask = block_mask(T, orders)
+    want = _oracle_step(u0, w, orders=orders)
+    want_a = _oracle_step(u0, w, adjoint=True, orders=orders)
+    plan = _plan(w, grid=False)
+    for i in range(plan.schedule_count(S)):
+        plan.set_schedule(S, i)
+        print(f"  schedule {i}", flush=True)
+        got = plan.step(_gpu(u0, torch_dev)).cpu().numpy()
+        assert_parity(got[:, :, mask], want[:, :, mask], what=f"T{T} schedule {i}")
+        got_a = plan.step_adjoint(_gpu(u0, torch_dev)).cpu().numpy()
+        assert_parity(got_a[:, :, mask], want_a[:, :, mask], what=f"T{T} adjoint schedule {i}")
+    got = plan.step_per_term(_gpu(u0, torch_dev)).cpu().numpy()
+    assert_parity(got[:, :, mask], want[:, :, mask], what=f"T{T} per-term")
+
+
 def test_multistep_and_adjoint(torch_dev):
     w = synth.Workload("ms", T=20, nlat=0, nlon=0, dt=3600.0, M=64, states=2)
     u0 = synth.random_state(w.T, 2, 7)
