@@ -264,9 +264,10 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     const int st = it.tile;
     const int npos = P * SE;
 
-    // ---- stage the item's constants and right-hand sides in LDS as four
-    // double2 chunks per position, [t][chunk][slot], so that the lanes of a row
-    // read consecutive 16-byte words: (th, om), (c_left, c_right), r_var, r_Phi
+    // ---- stage the item's constants and right-hand sides in LDS as eight
+    // planes of doubles per position, [t][plane][slot], so that the lanes of a
+    // row read consecutive 8-byte words (8-byte reads issue far faster here than
+    // 16-byte ones): th, om, c_left, c_right, Re/Im r_var, Re/Im r_Phi
     double2* c = reinterpret_cast<double2*>(sm);
     for (int j = tid; j < npos; j += blockDim.x) {
         const int l2 = j / SE, t2 = j - l2 * SE;
@@ -280,11 +281,15 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
             v2 = A.ch_var[st * A.var_stride + mi.slot_base + (long long)p * L + j];
             if ((n + p) & 1) v3 = A.ch_phi[st * A.nspec + i];
         }
-        double2* o = c + (size_t)(t2 * 4) * PS + s2;
-        o[0] = v0;
-        o[PS] = v1;
-        o[2 * PS] = v2;
-        o[3 * PS] = v3;
+        double* o = sm + (size_t)(t2 * 8) * PS + s2;
+        o[0] = v0.x;
+        o[PS] = v0.y;
+        o[2 * PS] = v1.x;
+        o[3 * PS] = v1.y;
+        o[4 * PS] = v2.x;
+        o[5 * PS] = v2.y;
+        o[6 * PS] = v3.x;
+        o[7 * PS] = v3.y;
     }
     __syncthreads();
 
@@ -298,17 +303,27 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
 
     const int stride = W * G;
 
-    // staged data of position t of this lane
+    // staged data of position t of this lane.  om and r_Phi exist only on
+    // divergence positions; the right coupling of position t is the left one
+    // of t + 1, so it is read only where that position is not read anyway.
     struct Pos {
-        double2 c0, c1, rv, rp;
+        double th, om, cl, cr;
+        cd rv, rp;
     };
-    auto fetch = [&](int t) {
-        const double2* o = c + (size_t)(t * 4) * PS + slot;
+    auto fetch = [&](int t, bool with_cr) {
+        const double* o = sm + (size_t)(t * 8) * PS + slot;
         Pos x;
-        x.c0 = o[0];
-        x.c1 = o[PS];
-        x.rv = o[2 * PS];
-        x.rp = ((PH + t) & 1) ? o[3 * PS] : make_double2(0.0, 0.0);
+        x.th = o[0];
+        x.cl = o[2 * PS];
+        x.cr = with_cr ? o[3 * PS] : 0.0;
+        x.rv = cd{o[4 * PS], o[5 * PS]};
+        if ((PH + t) & 1) {
+            x.om = o[PS];
+            x.rp = cd{o[6 * PS], o[7 * PS]};
+        } else {
+            x.om = 0.0;
+            x.rp = mk(0, 0);
+        }
         return x;
     };
     // Latency hiding where registers allow (row groups): the pole and its
@@ -352,36 +367,37 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         auto element = [&](int t, const Pos& x, cd& b, double& ca, double& cb, cd& du, cd& dw) {
             const double sg = ((PH + t) & 1) ? 1.0 : -1.0;  // divergence rows +, vorticity rows -
             const double ts = (t & 1) ? -1.0 : 1.0;         // (-1)^t
-            ca = sg * x.c1.x;
-            cb = sg * x.c1.y;
+            ca = sg * x.cl;
+            cb = sg * x.cr;
             if ((PH + t) & 1) {
                 // divergence element, Phi eliminated: diagonal alpha + i th + om^2/alpha,
                 // right-hand side r_div - (om/alpha) r_Phi
-                const double om = x.c0.y;
+                const double om = x.om;
                 const cd f = cscale(ai, om);
-                b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, x.c0.x));
-                du = cfms(cd{x.rv.x, x.rv.y}, f, cd{x.rp.x, x.rp.y});
-                const double wr = fma(f.r, x.rp.x, fma(f.i, x.rp.y, x.rv.x));
-                const double wi = fma(f.i, x.rp.x, fma(-f.r, x.rp.y, -x.rv.y));
+                b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, x.th));
+                du = cfms(x.rv, f, x.rp);
+                const double wr = fma(f.r, x.rp.r, fma(f.i, x.rp.i, x.rv.r));
+                const double wi = fma(f.i, x.rp.r, fma(-f.r, x.rp.i, -x.rv.i));
                 dw = cd{ts * wr, ts * wi};
             } else {
-                b = mk(al.r, al.i + x.c0.x);
-                du = cd{x.rv.x, x.rv.y};
-                dw = cd{ts * x.rv.x, -ts * x.rv.y};
+                b = mk(al.r, al.i + x.th);
+                du = x.rv;
+                dw = cd{ts * x.rv.r, -ts * x.rv.i};
             }
         };
         // forward sweep (with kAhead the next position's data is read before
         // this one's work)
         Pos cur;
-        if constexpr (kAhead) cur = fetch(0);
+        if constexpr (kAhead) cur = fetch(0, false);
 #pragma unroll
         for (int t = 0; t < NI; ++t) {
             Pos nxt;
             if constexpr (kAhead) {
-                nxt = fetch(t + 1);
+                nxt = fetch(t + 1, t + 1 == SE - 1);
                 __builtin_amdgcn_sched_barrier(0);
+                cur.cr = nxt.cl;
             } else {
-                cur = fetch(t);
+                cur = fetch(t, true);
             }
             cd b, du, dw;
             double ca, cb;
@@ -417,7 +433,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         // the right neighbour's values enter with cI, which is zero at a chain end
         cd bI, dIu, dIw;
         double aI, cI;
-        if constexpr (!kAhead) cur = fetch(SE - 1);
+        if constexpr (!kAhead) cur = fetch(SE - 1, true);
         element(SE - 1, cur, bI, aI, cI, dIu, dIw);
         typedef Mover<KIND, 1> M1;
         const cd vN = M1::above(v0, lane), wN = M1::above(w0, lane);
