@@ -109,14 +109,14 @@ constexpr int kWaves = 4;   // waves per workgroup; they share one item's staged
 constexpr int kStage = 8;   // doubles staged per chain position
 
 __device__ __forceinline__ cd crcp_newton(cd a) {
-    // 1/(x + i y) = (x - i y)/(x^2 + y^2); the real reciprocal by v_rcp_f64 and
-    // two Newton-Raphson steps r <- r + r (1 - d r).
+    // 1/(x + i y) = (x - i y)/(x^2 + y^2).  The real reciprocal r of v_rcp_f64
+    // (relative error ~5e-8 here) is refined with one third-order step,
+    // r <- r (1 + e + e^2), e = 1 - d r: the error becomes ~e^3 plus rounding,
+    // one fma fewer than two Newton steps.
     const double d = fma(a.r, a.r, a.i * a.i);
-    double r = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
+    const double r0 = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r0, 1.0);
+    const double r = fma(r0, fma(e, e, e), r0);
     return cd{a.r * r, -a.i * r};
 }
 
