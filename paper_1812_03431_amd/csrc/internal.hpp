@@ -40,9 +40,11 @@ Poles make_poles(int M, double h, int L, int normalize);
 // Gauss-Legendre nodes (descending, north to south) and weights.
 void gauss_legendre(int nlat, std::vector<double>& mu, std::vector<double>& w);
 
-// Orthonormal P_n^m(mu_j): returned as [m][n-m][j] packed by m-blocks,
-// block m at offset spec_offset(T, m) * nlat.
-std::vector<double> legendre_table(int T, const std::vector<double>& mu);
+// Recurrence coefficients (a_n, b_n) of the orthonormal P_n^m, [nspec][2], and
+// exact restart rows (P_{n0-1}, P_{n0}) at n0 = m + run r, [row][2][nmu] with
+// row = run_base[m] + r (run_base has T + 2 entries).
+std::vector<double> legendre_coefs(int T);
+std::vector<double> legendre_restarts(int T, int run, const std::vector<double>& mu, std::vector<int>& run_base);
 
 __host__ __device__ inline long long spec_offset(int T, int m) {
     return (long long)m * (T + 1) - (long long)m * (m - 1) / 2;
@@ -139,7 +141,9 @@ struct rexi_plan {
     // transforms
     int nlat = 0, nlon = 0, nhalf = 0;
     std::vector<double> mu, w;
-    double* d_plm = nullptr;      // Legendre table for the transforms
+    double* d_restart = nullptr;  // Legendre restart rows [row][2][nhalf]
+    double* d_lcoef = nullptr;    // Legendre recurrence coefficients [nspec][2]
+    double* d_mu = nullptr;       // northern Gauss nodes [nhalf]
     double* d_wts = nullptr;      // Gauss weights
     double* d_four = nullptr;     // Fourier coefficients workspace [T+1][nlat][2B]
     double2* d_twiddle = nullptr; // FFT twiddles

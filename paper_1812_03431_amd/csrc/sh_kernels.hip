@@ -8,9 +8,9 @@
 // LDS.  Latitude: per zonal order m the Legendre sum is a small dense
 // contraction (T+1-m degrees x nlat/2 latitudes x 2B real columns) and runs
 // on FP64 MFMA (v_mfma_f64_16x16x4f64).  Gauss latitudes are symmetric about
-// the equator and P_n^m(-mu) = (-1)^{n-m} P_n^m(mu), so only the northern
-// half of the table is stored and each sum splits into an even part
-// (F_j + F_{j'}) and an odd part (F_j - F_{j'}), j' = nlat-1-j.
+// the equator and P_n^m(-mu) = (-1)^{n-m} P_n^m(mu), so only northern
+// latitudes are used and each sum splits into an even part (F_j + F_{j'}) and
+// an odd part (F_j - F_{j'}), j' = nlat-1-j.
 //
 // Workspace layout of the Fourier coefficients: Fw[m][j][c], c = 2b + {0: re, 1: im}.
 #include <hip/hip_runtime.h>
@@ -25,14 +25,13 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr size_t kLdsBytes = 64 * 1024;  // LDS per workgroup used by the Legendre kernels
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
 // In-place radix-2 decimation-in-time FFT of X[0..n) in LDS (input already
 // in bit-reversed order).  tw[k] = exp(-2 pi i k / n), k < n/2; conj for the
 // inverse direction.
-__device__ void fft_lds(double2* X, const double2* __restrict__ tw, int n, bool inverse) {
+__device__ void fft_lds(double2* X, const double2* tw, int n, bool inverse) {
     for (int len = 2; len <= n; len <<= 1) {
         const int half = len >> 1;
         const int step = n / len;
@@ -54,13 +53,31 @@ __device__ void fft_lds(double2* X, const double2* __restrict__ tw, int n, bool 
 __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ grid, double* __restrict__ Fw,
                                                      const double2* __restrict__ tw, int nlat, int nlon, int bits,
                                                      int T, int C) {
-    extern __shared__ double2 X[];
+    extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
+    double2* tws = X + nlon;
     const int row = blockIdx.x;  // b * nlat + j
     const int b = row / nlat, j = row - b * nlat;
     const double* src = grid + (long long)row * nlon;
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) X[bitrev(k, bits)] = make_double2(src[k], 0.0);
+    // all loads of this thread issued before any store (one memory latency)
+    constexpr int kU = 8;
+    for (int k0 = 0; k0 < nlon; k0 += kU * 256) {
+        double v[kU];
+        double2 t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * 256 + threadIdx.x;
+            v[u] = (k < nlon) ? src[k] : 0.0;
+            t[u] = (k < nlon / 2) ? tw[k] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * 256 + threadIdx.x;
+            if (k < nlon) X[bitrev(k, bits)] = make_double2(v[u], 0.0);
+            if (k < nlon / 2) tws[k] = t[u];
+        }
+    }
     __syncthreads();
-    fft_lds(X, tw, nlon, false);
+    fft_lds(X, tws, nlon, false);
     const double inv = 1.0 / nlon;
     for (int m = threadIdx.x; m <= T; m += blockDim.x) {
         const double2 v = X[m];
@@ -74,10 +91,12 @@ __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ 
 __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ Fw, double* __restrict__ grid,
                                                      const double2* __restrict__ tw, int nlat, int nlon, int bits,
                                                      int T, int C) {
-    extern __shared__ double2 X[];
+    extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
+    double2* tws = X + nlon;
     const int row = blockIdx.x;
     const int b = row / nlat, j = row - b * nlat;
     for (int k = threadIdx.x; k < nlon; k += blockDim.x) X[k] = make_double2(0.0, 0.0);
+    for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
     __syncthreads();
     // spectrum of the real field: X[m] += F_m, X[n-m] += conj(F_m), X[0] = Re F_0
     for (int m = threadIdx.x; m <= T; m += blockDim.x) {
@@ -102,114 +121,153 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
         }
     }
     __syncthreads();
-    fft_lds(X, tw, nlon, true);
+    fft_lds(X, tws, nlon, true);
     double* dst = grid + (long long)row * nlon;
     for (int k = threadIdx.x; k < nlon; k += blockDim.x) dst[k] = X[k].x;
 }
 
-// A run of Legendre tiles of one order m for one workgroup of four waves.
-// Forward: tiles [t0, t1) over the even-parity degree tiles followed by the
-// odd ones (16 degrees each), two per wave.  Inverse: tiles of 16
-// latitudes, one per wave.
+// Legendre contractions with P_n^m generated on the device.  The table
+// itself (34 MB at T256) is never stored: P follows from the three-term
+// recurrence P_n = a_n mu P_{n-1} - b_n P_{n-2}, restarted every kRun degrees
+// from exact host values, which keeps the FP64 recurrence error at a few ulp.
+constexpr int kRun = 64;         // degrees per restart run
+constexpr int kPhase = 32;       // degrees generated per forward phase (two 16-row parity tiles)
+constexpr int kPD = kPhase + 1;  // LDS row length of a generated tile (odd: spreads banks)
+constexpr int kLatBlock = 64;    // latitudes generated per forward block
+
+// Forward work: one run of order m.  Inverse work: latitude tiles [t0, t1) of
+// order m (one wave each); run0 = first restart row of m.
+struct LegRun {
+    int m, n0, row, pad;
+};
 struct LegWork {
-    int m, t0, t1, pad;
+    int m, t0, t1, run0;
 };
 
-// Forward: out[b][idx(m, n)] = sum_{j<H} P[m][n][j] w_j (F_j +- F_j')  (+ even, - odd).
-// The weighted even/odd Fourier blocks of m, E and O [H][C], are staged in
-// LDS once per workgroup.  MFMA k index: within a block of 16 latitudes J,
-// lane group kq at k-step s takes latitude J + 4 kq + s, so each lane reads
-// four consecutive table entries of its degree.  Each wave keeps four
-// independent accumulators (two degree tiles x two column tiles) in flight.
-__global__ void __launch_bounds__(256) k_legendre_forward(const LegWork* __restrict__ work,
-                                                          const double* __restrict__ plm,
+// Forward: out[b][idx(m, n)] = sum_{j<H} P_n^m(mu_j) w_j (F_j +- F_j'), + for
+// n - m even, - for odd, over the degrees n0 .. n0 + kRun - 1 of one run.
+// Staged once in LDS: the weighted even/odd Fourier blocks E, O [H][C], the
+// run's recurrence coefficients (zero beyond T) and the recurrence state of
+// every latitude.  Per phase of 32 degrees and block of kLatBlock latitudes,
+// the first kLatBlock threads generate P (one latitude each) into Pt[lat][d];
+// then wave w accumulates output tile w (row tile = degree parity within the
+// phase, 16 columns) on MFMA, k running over latitudes.  Columns
+// [c_off, c_off + C) of the Fourier block (row stride Cs), C <= 32.
+__global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restrict__ runs,
+                                                          const double* __restrict__ restart,
+                                                          const double2* __restrict__ coef,
+                                                          const double* __restrict__ mu,
                                                           const double* __restrict__ wts,
                                                           const double* __restrict__ Fw, double* __restrict__ spec,
                                                           int T, int nlat, int H, int Cs, int c_off, int C) {
-    // columns [c_off, c_off + C) of the Fourier block (row stride Cs)
     extern __shared__ double lds[];
-    const LegWork wk = work[blockIdx.x];
-    const int m = wk.m;
-    double* E = lds;            // [H][C]
-    double* O = lds + H * C;    // [H][C]
-    for (int idx = threadIdx.x; idx < H * C; idx += blockDim.x) {
-        const int j = idx / C, c = idx - j * C;
-        const double f1 = Fw[((long long)m * nlat + j) * Cs + c_off + c];
-        const double f2 = Fw[((long long)m * nlat + (nlat - 1 - j)) * Cs + c_off + c];
-        E[idx] = wts[j] * (f1 + f2);
-        O[idx] = wts[j] * (f1 - f2);
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const LegRun rn = runs[blockIdx.x];
+    const int m = rn.m, n0 = rn.n0;
+    const int tid = threadIdx.x;
     const long long so = spec_offset(T, m);
     const long long ns = nspec_of(T);
-    const int L = T + 1 - m;
-    const int ne = ((L + 1) / 2 + 15) / 16;  // even-parity tiles
-    const int row = lane & 15, kq = lane >> 4;
-    for (int tb = wk.t0 + 2 * wave; tb < wk.t1; tb += 8) {
-        int e[2], i0[2], nrow[2];
-        bool rok[2];
-        const double* prow[2];
-        const double* B[2];
+    double* E = lds;                                  // [H][C]
+    double* O = E + H * C;                            // [H][C]
+    double* Pt = O + H * C;                           // [kLatBlock][kPD]
+    double2* st = reinterpret_cast<double2*>(Pt + kLatBlock * kPD);  // [H]: (P_{n-1}, P_n)
+    // coefficients of degree n0 + k: a separate LDS object, so that the
+    // compiler sees they cannot alias the generated tile
+    __shared__ double2 cf[kRun + 1];
+    // staging: every thread issues kU loads before its stores (one latency)
+    constexpr int kU = 8;
+    for (int i0 = 0; i0 < H * C; i0 += kU * 256) {
+        double f1[kU], f2[kU], wj[kU];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int t = tb + u;
-            const bool tile_ok = t < wk.t1;
-            e[u] = (tile_ok && t >= ne) ? 1 : 0;
-            i0[u] = tile_ok ? (t - (e[u] ? ne : 0)) * 16 : 0;
-            nrow[u] = m + e[u] + 2 * (i0[u] + row);
-            rok[u] = tile_ok && nrow[u] <= T;
-            prow[u] = plm + (so + (rok[u] ? nrow[u] - m : 0)) * H;
-            B[u] = e[u] ? O : E;
+        for (int u = 0; u < kU; ++u) {
+            const int idx = i0 + u * 256 + tid;
+            const bool ok = idx < H * C;
+            const int j = ok ? idx / C : 0, c = ok ? idx - j * C : 0;
+            f1[u] = ok ? Fw[((long long)m * nlat + j) * Cs + c_off + c] : 0.0;
+            f2[u] = ok ? Fw[((long long)m * nlat + (nlat - 1 - j)) * Cs + c_off + c] : 0.0;
+            wj[u] = ok ? wts[j] : 0.0;
         }
-        for (int c0 = 0; c0 < C; c0 += 32) {
-            const int col0 = c0 + (lane & 15), col1 = col0 + 16;
-            const bool ok0 = col0 < C, ok1 = col1 < C;
-            v4d acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
-                             {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
-            for (int J = 0; J < H; J += 16) {
-                const int jb = J + 4 * kq;
-                double a[2][4];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < kU; ++u) {
+            const int idx = i0 + u * 256 + tid;
+            if (idx < H * C) {
+                E[idx] = wj[u] * (f1[u] + f2[u]);
+                O[idx] = wj[u] * (f1[u] - f2[u]);
+            }
+        }
+    }
+    for (int j = tid; j < H; j += blockDim.x)
+        st[j] = make_double2(restart[((long long)rn.row * 2) * H + j], restart[((long long)rn.row * 2 + 1) * H + j]);
+    for (int k = tid; k <= kRun; k += blockDim.x)
+        cf[k] = (k >= 1 && n0 + k <= T) ? coef[so + (n0 + k - m)] : make_double2(0.0, 0.0);
+    const int nend = min(T, n0 + kRun - 1);
+    const int lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int nct = (C + 15) / 16;       // column tiles (<= 2)
+    const int tl = wave;                 // this wave's output tile, if any
+    const bool has_tile = tl < 2 * nct;
+    const int r = tl & 1, h = tl >> 1;   // row tile (degree parity in the phase), column tile
+    const int col = h * 16 + row;        // B / D column of this lane
+    const bool cok = has_tile && col < C;
+    const double* Bm = r ? O : E;        // (ph - m) is even, so the parity of n - m is r
+    for (int ph = n0; ph <= nend; ph += kPhase) {
+        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int lb = 0; lb < H; lb += kLatBlock) {
+            const int nl = min(kLatBlock, H - lb);
+            __syncthreads();  // staging done / previous block consumed
+            if (tid < nl) {
+                const int j = lb + tid;
+                const double x = mu[j];
+                double2 pc = st[j];
+                const int k0 = ph - n0;  // cf index of degree ph is k0; step n -> n+1 uses k + 1
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) a[u][s] = (rok[u] && jb + s < H) ? prow[u][jb + s] : 0.0;
+                for (int d = 0; d < kPhase; ++d) {
+                    Pt[tid * kPD + d] = (ph + d <= nend) ? pc.y : 0.0;
+                    const double2 ab = cf[min(k0 + d + 1, kRun)];
+                    pc = make_double2(pc.y, fma(ab.x * x, pc.y, -ab.y * pc.x));
+                }
+                st[j] = pc;
+            }
+            __syncthreads();
+            if (has_tile) {
+                // the block's 16 k-steps: all fragment reads first, then the MFMAs
+                constexpr int kSteps = kLatBlock / 4;
+                double av[kSteps], bv[kSteps];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const bool jok = jb + s < H;
+                for (int q = 0; q < kSteps; ++q) {
+                    const int lat = (q >> 2) * 16 + 4 * kq + (q & 3);  // < kLatBlock
+                    const bool lok = lat < nl;
+                    av[q] = lok ? Pt[lat * kPD + 2 * row + r] : 0.0;
+                    bv[q] = (lok && cok) ? Bm[(lb + min(lat, nl - 1)) * C + col] : 0.0;
+                }
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        const double b0 = (ok0 && jok) ? B[u][(jb + s) * C + col0] : 0.0;
-                        const double b1 = (ok1 && jok) ? B[u][(jb + s) * C + col1] : 0.0;
-                        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b0, acc[u][0], 0, 0, 0);
-                        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b1, acc[u][1], 0, 0, 0);
-                    }
+                for (int q = 0; q < kSteps; ++q) {
+                    if (q & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc1, 0, 0, 0);
+                    else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
                 }
             }
-            // accumulator register r of lane l holds D[4 r + l/16][l % 16]
+        }
+        // accumulator register rr of lane l holds D[4 rr + l/16][l % 16]
+        if (cok) {
+            const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int col = h ? col1 : col0;
-                    if (!(h ? ok1 : ok0) || tb + u >= wk.t1) continue;
-                    const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int n = m + e[u] + 2 * (i0[u] + 4 * r + kq);
-                        if (n <= T) spec[((long long)b * ns + so + (n - m)) * 2 + ri] = acc[u][h][r];
-                    }
-                }
+            for (int rr = 0; rr < 4; ++rr) {
+                const int n = ph + 2 * (4 * rr + kq) + r;
+                if (n <= nend) spec[((long long)b * ns + so + (n - m)) * 2 + ri] = acc0[rr] + acc1[rr];
+            }
         }
     }
 }
 
-// Inverse: for 16 latitudes j (< H): Fe = sum_{n-m even} P S, Fo = sum_{odd} P S;
-// Fw[m][j] = Fe + Fo, Fw[m][j'] = Fe - Fo.  The spectral block of m, [L][C],
-// is staged in LDS once per workgroup; each wave keeps four independent
-// accumulators (two parities x two column tiles) in flight.
+// Inverse: Fw[m][j] = Fe + Fo, Fw[m][j'] = Fe - Fo with Fe / Fo the sums of
+// P_n^m(mu_j) S_n over n - m even / odd.  The spectral block of m, Sm [L][C],
+// is staged in LDS; each wave owns 16 latitudes.  Lanes (i = lane & 15,
+// kq = lane >> 4) run the recurrence of latitude i in registers (the four kq
+// lanes alike) and keep what their MFMA fragment needs: per k-step of 8
+// degrees base .. base + 7, A_even = P_{base + 2 kq}, A_odd = P_{base + 2 kq + 1}.
 __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restrict__ work,
-                                                          const double* __restrict__ plm,
+                                                          const double* __restrict__ restart,
+                                                          const double2* __restrict__ coef,
+                                                          const double* __restrict__ mu,
                                                           const double* __restrict__ spec,
                                                           double* __restrict__ Fw, int T, int nlat, int H, int Cs,
                                                           int c_off, int C) {
@@ -220,51 +278,116 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     const long long ns = nspec_of(T);
     const int L = T + 1 - m;
     double* Sm = lds;  // [L][C]
-    for (int idx = threadIdx.x; idx < L * C; idx += blockDim.x) {
-        const int d = idx / C, c = idx - d * C;
-        Sm[idx] = spec[((long long)((c_off + c) >> 1) * ns + so + d) * 2 + ((c_off + c) & 1)];
+    constexpr int kU = 8;  // loads in flight per thread while staging
+    for (int i0 = 0; i0 < L * C; i0 += kU * 256) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int idx = i0 + u * 256 + threadIdx.x;
+            const bool ok = idx < L * C;
+            const int d = ok ? idx / C : 0, c = ok ? idx - d * C : 0;
+            v[u] = ok ? spec[((long long)((c_off + c) >> 1) * ns + so + d) * 2 + ((c_off + c) & 1)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int idx = i0 + u * 256 + threadIdx.x;
+            if (idx < L * C) Sm[idx] = v[u];
+        }
     }
+    // recurrence coefficients of degree m + k, k < L + 8 (zero beyond T)
+    double2* cf = reinterpret_cast<double2*>(Sm + L * C);
+    for (int k = threadIdx.x; k < L + 8; k += blockDim.x)
+        cf[k] = (k >= 1 && k < L) ? coef[so + k] : make_double2(0.0, 0.0);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int kq = lane >> 4;
-    const int cnt0 = (L + 1) / 2, cnt1 = L / 2;  // degrees of each parity
-    for (int t = wk.t0 + wave; t < wk.t1; t += 4) {
-        const int j0 = t * 16;
-        const int jrow = j0 + (lane & 15);  // A row = latitude
-        const bool lat_ok = jrow < H;
-        for (int c0 = 0; c0 < C; c0 += 32) {
-            const int col0 = c0 + (lane & 15), col1 = col0 + 16;
-            const bool ok0 = col0 < C, ok1 = col1 < C;
-            v4d acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
-                             {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
-            for (int i0 = 0; i0 < cnt0; i0 += 4) {
-                const int i = i0 + kq;
+    const int t = wk.t0 + wave;
+    if (t >= wk.t1) return;  // no latitude tile for this wave (no barrier follows)
+    const int i = lane & 15, kq = lane >> 4;
+    const int j = t * 16 + i;
+    const bool jok = j < H;
+    const double x = jok ? mu[j] : 0.0;
+    const int nct = (C + 15) / 16;  // <= 2
+    v4d ae0 = {0.0, 0.0, 0.0, 0.0}, ao0 = ae0, ae1 = ae0, ao1 = ae0;
+    // restart rows of run 0, and of run rr + 1 read while run rr is worked on
+    double pv_n = jok ? restart[((long long)wk.run0 * 2) * H + j] : 0.0;
+    double cu_n = jok ? restart[((long long)wk.run0 * 2 + 1) * H + j] : 0.0;
+    for (int rr = 0; m + kRun * rr <= T; ++rr) {
+        const int n0 = m + kRun * rr;
+        double pv = pv_n, cu = cu_n;
+        if (m + kRun * (rr + 1) <= T && jok) {
+            const int row = wk.run0 + rr + 1;
+            pv_n = restart[((long long)row * 2) * H + j];
+            cu_n = restart[((long long)row * 2 + 1) * H + j];
+        }
+        const int nend = min(T, n0 + kRun - 1);
+        for (int base = n0; base <= nend; base += 8) {
+            double a_e = 0.0, a_o = 0.0;
+            const int kb = base - m;  // cf index of degree base
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const bool iok = i < (e ? cnt1 : cnt0);
-                    const int d = e + 2 * i;
-                    const double a = (iok && lat_ok) ? plm[(so + d) * H + jrow] : 0.0;
-                    const double b0 = (iok && ok0) ? Sm[d * C + col0] : 0.0;
-                    const double b1 = (iok && ok1) ? Sm[d * C + col1] : 0.0;
-                    acc[e][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[e][0], 0, 0, 0);
-                    acc[e][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[e][1], 0, 0, 0);
-                }
+            for (int d = 0; d < 8; ++d) {
+                const double v = (base + d <= nend) ? cu : 0.0;
+                if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? v : a_e;
+                else a_o = (kq == (d >> 1)) ? v : a_o;
+                const double2 ab = cf[kb + d + 1];
+                const double nx = fma(ab.x * x, cu, -ab.y * pv);
+                pv = cu;
+                cu = nx;
             }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int col = h ? col1 : col0;
-                if (!(h ? ok1 : ok0)) continue;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = j0 + 4 * r + kq;
-                    if (j < H) {
-                        Fw[((long long)m * nlat + j) * Cs + c_off + col] = acc[0][h][r] + acc[1][h][r];
-                        Fw[((long long)m * nlat + (nlat - 1 - j)) * Cs + c_off + col] = acc[0][h][r] - acc[1][h][r];
-                    }
-                }
+            const int de = base - m + 2 * kq, dodd = de + 1;
+            const bool eok = de < L, ook = dodd < L;
+            {
+                const int col = i;
+                const bool cok = col < C;
+                const double be = (eok && cok) ? Sm[de * C + col] : 0.0;
+                const double bo = (ook && cok) ? Sm[dodd * C + col] : 0.0;
+                ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, be, ae0, 0, 0, 0);
+                ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bo, ao0, 0, 0, 0);
+            }
+            if (nct > 1) {
+                const int col = 16 + i;
+                const bool cok = col < C;
+                const double be = (eok && cok) ? Sm[de * C + col] : 0.0;
+                const double bo = (ook && cok) ? Sm[dodd * C + col] : 0.0;
+                ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, be, ae1, 0, 0, 0);
+                ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bo, ao1, 0, 0, 0);
             }
         }
     }
+    // accumulator register q of lane l holds D[4 q + l/16][l % 16]: latitude
+    // row 4 q + kq of the tile, column l % 16 of the column tile
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int col = hh * 16 + i;
+        if (hh >= nct || col >= C) continue;
+        const v4d ae = hh ? ae1 : ae0, ao = hh ? ao1 : ao0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = t * 16 + 4 * q + kq;
+            if (jj < H) {
+                Fw[((long long)m * nlat + jj) * Cs + c_off + col] = ae[q] + ao[q];
+                Fw[((long long)m * nlat + (nlat - 1 - jj)) * Cs + c_off + col] = ae[q] - ao[q];
+            }
+        }
+    }
+}
+
+constexpr size_t kLdsBytes = 96 * 1024;  // LDS per workgroup used by the Legendre kernels
+
+// LDS of the forward kernel besides E and O: generated tile, state, coefficients.
+size_t forward_fixed_lds(int H) {
+    return sizeof(double) * kLatBlock * kPD + sizeof(double2) * (size_t)H + sizeof(double2) * (kRun + 1);
+}
+// Largest column chunk (even, <= 32) whose LDS fits kLdsBytes.
+int forward_chunk(int H, int C) {
+    const size_t pt = forward_fixed_lds(H);
+    const size_t per_col = sizeof(double) * 2 * (size_t)H;
+    const int cc = (int)((kLdsBytes - pt) / per_col) & ~1;
+    return std::max(2, std::min(std::min(C, 32), cc));
+}
+int inverse_chunk(int T, int C) {
+    const size_t cfb = sizeof(double2) * (T + 1 + 8);
+    const int cc = (int)((kLdsBytes - cfb) / (sizeof(double) * (T + 1))) & ~1;
+    return std::max(2, std::min(std::min(C, 32), cc));
 }
 
 }  // namespace
@@ -272,56 +395,74 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
 int sh_setup(rexi_plan* pl) {
     const int T = pl->T, nlat = pl->prm.nlat, nlon = pl->prm.nlon;
     if (nlat % 2) return fail(REXI_EUNSUPPORTED, "nlat must be even");
+    if (nlat > 2048) return fail(REXI_EUNSUPPORTED, "nlat above 2048");
     if ((long long)nlon * 16 > 64 * 1024) return fail(REXI_EUNSUPPORTED, "nlon above 4096");
     pl->nlat = nlat;
     pl->nlon = nlon;
     pl->nhalf = nlat / 2;
+    const int H = pl->nhalf;
     gauss_legendre(nlat, pl->mu, pl->w);
-    std::vector<double> north(pl->mu.begin(), pl->mu.begin() + pl->nhalf);
-    std::vector<double> plm = legendre_table(T, north);
-    std::vector<double> wn(pl->w.begin(), pl->w.begin() + pl->nhalf);
+    std::vector<double> north(pl->mu.begin(), pl->mu.begin() + H);
+    std::vector<int> run_base;
+    std::vector<double> restart = legendre_restarts(T, kRun, north, run_base);
+    std::vector<double> lcoef = legendre_coefs(T);
+    std::vector<double> wn(pl->w.begin(), pl->w.begin() + H);
     std::vector<double2> tw(nlon / 2);
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int k = 0; k < nlon / 2; ++k) {
         const long double a = -2 * pi * k / nlon;
         tw[k] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    // work: runs of at most 8 tiles of one order (a workgroup of four waves)
-    std::vector<LegWork> tf, ti;
+    // forward: one workgroup per run, longest orders first (they come first);
+    // inverse: four latitude tiles (one per wave) of one order per workgroup
+    std::vector<LegRun> tf;
+    std::vector<LegWork> ti;
+    const int nl = (H + 15) / 16;
     for (int m = 0; m <= T; ++m) {
-        const int L = T + 1 - m;
-        const int nt = ((L + 1) / 2 + 15) / 16 + (L / 2 + 15) / 16;
-        for (int t0 = 0; t0 < nt; t0 += 8) tf.push_back(LegWork{m, t0, std::min(nt, t0 + 8), 0});
-        const int nl = (pl->nhalf + 15) / 16;
-        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), 0});
+        for (int r = 0; m + kRun * r <= T; ++r) tf.push_back(LegRun{m, m + kRun * r, run_base[m] + r, 0});
+        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m]});
     }
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes ? bytes : 1);
         if (e != hipSuccess) return fail(REXI_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
         return REXI_OK;
     };
-    int rc = alloc((void**)&pl->d_plm, plm.size() * sizeof(double));
+    int rc = alloc((void**)&pl->d_restart, restart.size() * sizeof(double));
+    if (!rc) rc = alloc((void**)&pl->d_lcoef, lcoef.size() * sizeof(double));
+    if (!rc) rc = alloc((void**)&pl->d_mu, north.size() * sizeof(double));
     if (!rc) rc = alloc((void**)&pl->d_wts, wn.size() * sizeof(double));
     if (!rc) rc = alloc((void**)&pl->d_twiddle, tw.size() * sizeof(double2));
     if (!rc) rc = alloc((void**)&pl->d_four, (size_t)(T + 1) * nlat * 2 * pl->prm.max_fields * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_tiles_f, tf.size() * sizeof(LegWork));
+    if (!rc) rc = alloc((void**)&pl->d_tiles_f, tf.size() * sizeof(LegRun));
     if (!rc) rc = alloc((void**)&pl->d_tiles_i, ti.size() * sizeof(LegWork));
     if (rc) return rc;
-    REXI_HIP(hipMemcpy(pl->d_plm, plm.data(), plm.size() * sizeof(double), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_restart, restart.data(), restart.size() * sizeof(double), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_lcoef, lcoef.data(), lcoef.size() * sizeof(double), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_mu, north.data(), north.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_wts, wn.data(), wn.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
-    REXI_HIP(hipMemcpy(pl->d_tiles_f, tf.data(), tf.size() * sizeof(LegWork), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_tiles_f, tf.data(), tf.size() * sizeof(LegRun), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_tiles_i, ti.data(), ti.size() * sizeof(LegWork), hipMemcpyHostToDevice));
     pl->ntiles_f = (int)tf.size();
     pl->ntiles_i = (int)ti.size();
+    // dynamic LDS above 64 KB per workgroup
+    const int fft_lds = (nlon + nlon / 2) * (int)sizeof(double2);
+    REXI_HIP(hipFuncSetAttribute((const void*)k_fft_forward, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
+    REXI_HIP(hipFuncSetAttribute((const void*)k_fft_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
+    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_forward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kLdsBytes));
+    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kLdsBytes));
     return REXI_OK;
 }
 
 void sh_release(rexi_plan* pl) {
-    void* ptrs[] = {pl->d_plm, pl->d_wts, pl->d_twiddle, pl->d_four, pl->d_tiles_f, pl->d_tiles_i};
+    void* ptrs[] = {pl->d_restart, pl->d_lcoef, pl->d_mu, pl->d_wts, pl->d_twiddle, pl->d_four, pl->d_tiles_f, pl->d_tiles_i};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    pl->d_plm = nullptr;
+    pl->d_restart = nullptr;
+    pl->d_lcoef = nullptr;
+    pl->d_mu = nullptr;
     pl->d_wts = nullptr;
     pl->d_twiddle = nullptr;
     pl->d_four = nullptr;
@@ -341,34 +482,35 @@ int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStr
     const size_t na = forward ? gbytes : sbytes, no = forward ? sbytes : gbytes;
     if (a < o + no && o < a + na) return fail(REXI_EALIAS, "output overlaps input");
     const int C = 2 * B;
+    const int H = pl->nhalf;
     int bits = 0;
     while ((1 << bits) < pl->nlon) ++bits;
-    const size_t lds = (size_t)pl->nlon * sizeof(double2);
+    const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
+    const double2* coef = reinterpret_cast<const double2*>(pl->d_lcoef);
     if (forward) {
         hipLaunchKernelGGL(k_fft_forward, dim3(B * pl->nlat), dim3(256), lds, s, (const double*)in, pl->d_four,
                            pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);
         REXI_HIP(hipGetLastError());
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_FWD, s));
-        // column chunks whose E/O blocks fit 64 KB of LDS
-        const int cc = std::max(2, std::min(C, (int)(kLdsBytes / (2 * sizeof(double) * pl->nhalf)) & ~1));
+        const int cc = forward_chunk(H, C);
         for (int c0 = 0; c0 < C; c0 += cc) {
             const int w = std::min(cc, C - c0);
-            const size_t lf = sizeof(double) * 2 * (size_t)pl->nhalf * w;
+            const size_t lf = sizeof(double) * 2 * (size_t)H * w + forward_fixed_lds(H);
             hipLaunchKernelGGL(k_legendre_forward, dim3(pl->ntiles_f), dim3(256), lf, s,
-                               (const LegWork*)pl->d_tiles_f, pl->d_plm, pl->d_wts, pl->d_four, (double*)out,
-                               pl->T, pl->nlat, pl->nhalf, C, c0, w);
+                               (const LegRun*)pl->d_tiles_f, pl->d_restart, coef, pl->d_mu, pl->d_wts, pl->d_four,
+                               (double*)out, pl->T, pl->nlat, H, C, c0, w);
             REXI_HIP(hipGetLastError());
         }
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_FWD, s));
     } else {
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_INV, s));
-        const int cc = std::max(2, std::min(C, (int)(kLdsBytes / (sizeof(double) * (pl->T + 1))) & ~1));
+        const int cc = inverse_chunk(pl->T, C);
         for (int c0 = 0; c0 < C; c0 += cc) {
             const int w = std::min(cc, C - c0);
-            const size_t li = sizeof(double) * (size_t)(pl->T + 1) * w;
+            const size_t li = sizeof(double) * (size_t)(pl->T + 1) * w + sizeof(double2) * (pl->T + 1 + 8);
             hipLaunchKernelGGL(k_legendre_inverse, dim3(pl->ntiles_i), dim3(256), li, s,
-                               (const LegWork*)pl->d_tiles_i, pl->d_plm, (const double*)in, pl->d_four, pl->T,
-                               pl->nlat, pl->nhalf, C, c0, w);
+                               (const LegWork*)pl->d_tiles_i, pl->d_restart, coef, pl->d_mu, (const double*)in,
+                               pl->d_four, pl->T, pl->nlat, H, C, c0, w);
             REXI_HIP(hipGetLastError());
         }
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_INV, s));
