@@ -108,6 +108,16 @@ def rexi_block_matrix(T, m, dt, co, a, omega, phibar, fsphere=None):
     return (R / d[:, None]) * d[None, :]
 
 
+def rexi_propagator(T, m, dt, co, a, omega, phibar, fsphere=None):
+    """The step restricted to order m as a dense matrix, physical units: the
+    banded solves of ``rexi_step`` applied to the identity (every column at once)."""
+    Lh = op.scaled_block(T, m, a, omega, phibar, fsphere=fsphere)
+    d = op.scaling_block(T, m, a, phibar)
+    Rs = _rexi_block(np.eye(Lh.shape[0], dtype=np.complex128), _band(dt * Lh),
+                     co["alpha"], co["beta_plus"], co["beta_minus"])
+    return (Rs / d[:, None]) * d[None, :]
+
+
 def dense_adjoint_run(g, nsteps, T, dt, co, a, omega, phibar):
     """g0 = (R^H)^nsteps g for every order m, with R_m^H = conj(R_m).T."""
     g = np.asarray(g, dtype=np.complex128)

@@ -39,7 +39,7 @@ class Workload:
     states: int = 1
     steps: int = 1
     checkpoint_every: int = 0
-    kind: str = "random"          # "random" | "jet"
+    kind: str = "random"          # "random" | "jet" | "bumps"
 
     def as_dict(self):
         return asdict(self)
@@ -55,6 +55,17 @@ WORKLOADS = {
                              checkpoint_every=8),
     "t256_fwd_adj": Workload("t256_fwd_adj", 256, 256, 512, 10800.0, 1024, states=4, steps=16,
                              checkpoint_every=4),
+}
+
+
+# The propagating Gaussian bumps of Section 6.2 over 1.5 days (129600 s) at the
+# paper's T128 (degrees n <= 127), with the T-REXI settings of its timing study
+# (Section 6.4): 800 s steps with M = 512, 1600 s steps with M = 1024, and one
+# 1.5-day step with M = 4096.  Fields at rest with the bump height.
+BUMP_WORKLOADS = {
+    "t127_bumps_dt800": Workload("t127_bumps_dt800", 127, 128, 256, 800.0, 512, steps=162, kind="bumps"),
+    "t127_bumps_dt1600": Workload("t127_bumps_dt1600", 127, 128, 256, 1600.0, 1024, steps=81, kind="bumps"),
+    "t127_bumps_1step": Workload("t127_bumps_1step", 127, 128, 256, 129600.0, 4096, steps=1, kind="bumps"),
 }
 
 
@@ -168,3 +179,21 @@ def bump_height(mu: np.ndarray, nlon: int, H: float = MEAN_DEPTH) -> np.ndarray:
         d = np.arccos(np.clip(cosd, -1.0, 1.0))
         out = out + np.exp(-d * d * p) * 0.1 * H
     return out
+
+
+def gauss_nodes(nlat: int) -> np.ndarray:
+    """sin(latitude) of the nlat Gauss-Legendre grid rows, north to south
+    (numpy's Gauss-Legendre nodes; the grid the inputs are sampled on)."""
+    x, _ = np.polynomial.legendre.leggauss(nlat)
+    return np.sort(x)[::-1].copy()
+
+
+def bump_fields(nlat: int, nlon: int, g: float = GRAVITY, H: float = MEAN_DEPTH) -> np.ndarray:
+    """Initial grid fields of the bump test, [3][nlat][nlon]: the geopotential
+    perturbation g (h - H) of ``bump_height`` and zero vorticity and divergence
+    (the fluid starts at rest)."""
+    mu = gauss_nodes(nlat)
+    out = np.zeros((3, nlat, nlon))
+    out[0] = g * (bump_height(mu, nlon, H) - H)
+    return out
+

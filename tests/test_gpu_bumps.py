@@ -1,0 +1,46 @@
+"""The Gaussian-bump workload (Section 6.2) through the whole GPU path: SH
+analysis of the bump fields, 1.5 days of T-REXI steps, against the oracle on
+sampled orders (the oracle's step as a matrix, raised to the step count)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operator as op, rexi as orexi, sh as osh
+from tests.gpu_common import A, OM, PB, assert_parity, block_mask, oracle_coeffs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.nodeid}", flush=True)
+
+
+@pytest.mark.parametrize("name,orders", [
+    ("t127_bumps_dt800", [64, 127]),
+    ("t127_bumps_dt1600", [64, 127]),
+    ("t127_bumps_1step", [0, 1, 64, 127]),
+])
+def test_bumps_over_one_and_a_half_days(name, orders):
+    import torch
+    import paper_1812_03431_amd as rexi
+    w = synth.BUMP_WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    fields = synth.bump_fields(w.nlat, w.nlon)
+    plan = rexi.plan_for(w, max_states=1, max_fields=3)
+    u0 = plan.sh_forward(torch.from_numpy(fields).to(dev)).view(1, 3, plan.nspec)
+    got = plan.step(u0, w.steps).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    # oracle: same grid through its own analysis, then R_m^steps per order
+    v0 = osh.analysis(fields, w.T)[None]
+    co = oracle_coeffs(w.M, w.h, w.L)
+    if w.steps == 1:
+        want = orexi.rexi_step(v0, w.T, w.dt, co, A, OM, PB, orders=orders)
+    else:
+        want = np.zeros_like(v0)
+        for m in orders:
+            R = orexi.rexi_propagator(w.T, m, w.dt, co, A, OM, PB)
+            blk = np.linalg.matrix_power(R, w.steps) @ op.block_of(v0, w.T, m)
+            op.scatter_block(want, blk, w.T, m)
+    mask = block_mask(w.T, orders)
+    assert_parity(got[:, :, mask], want[:, :, mask], what=f"{name} orders {orders}")
