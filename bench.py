@@ -14,8 +14,9 @@ The metric is (pole, m)-block solves per second over the timed region:
 Also reported: live HIP-event timing of the fused solve kernel (roofline
 against the FP64 vector peak), the FP64-MFMA Legendre kernels, the plain
 per-term launch form for comparison, the wall-clock of the Gaussian-bump
-workload over 1.5 days (Section 6.2), and the CPU oracle timed on a bounded
-sample of the same workload.
+workload over 1.5 days (Section 6.2), the f-sphere dispersion errors of the
+step (Section 6.3), and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -132,6 +133,19 @@ def bump_runs(rexi, synth, torch, dev, reps=3):
     out["paper_context"] = ("Cheyenne, Section 6.4 (other hardware, up to 512 MPI ranks; context only): "
                             "13.5 s for the best T-REXI run with M = 512, 2.02 s for one 1.5-day step with M = 4096")
     return out
+
+
+def dispersion_run(rexi, synth, torch, dev):
+    """Numerical dispersion of the step on the f-sphere (Section 6.3): every
+    mode stepped once on the GPU, log-eigenvalues against the exact frequencies."""
+    from paper_1812_03431_amd import dispersion
+    w, f0 = synth.DISPERSION_WORKLOAD, synth.FSPHERE_F0
+    plan = rexi.plan_for(w, max_states=64, grid=False, fsphere=f0)
+    t0 = time.perf_counter()
+    res = dispersion.analyse(plan, w.T, w.dt, f0, synth.GRAVITY * synth.MEAN_DEPTH, synth.EARTH_RADIUS, dev)
+    return {"T": w.T, "dt_s": w.dt, "M": w.M, "f0": f0, "modes": int(len(res["exact"])),
+            "max_rel_phase_error": res["max_rel_phase_error"], "max_abs_zero_mode_rad_s": res["max_abs_zero_mode"],
+            "max_abs_growth_per_s": res["max_abs_growth"], "seconds": time.perf_counter() - t0}
 
 
 def main():
@@ -282,6 +296,7 @@ def main():
         rec["copy_calibration_bytes"] = 1 << 30
     if not args.no_bumps:
         rec["bumps"] = bump_runs(rexi, synth, torch, dev)
+        rec["dispersion"] = dispersion_run(rexi, synth, torch, dev)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

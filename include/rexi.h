@@ -75,8 +75,18 @@ typedef struct rexi_plan rexi_plan;
  *   M, h, L           REXI: Gaussians per side, Gaussian width, half-width K of
  *                     the rational basis (Section 4.1); M >= 1, 0 < h, 1 <= L <= 32
  *   normalize         1: divide beta by the x = 0 response (Section 6.1), 0: raw
- *   max_states        largest S accepted by rexi_step / rexi_step_adjoint
- *   max_fields        largest B accepted by sh_forward / sh_inverse */
+ *   max_states        largest S accepted by rexi_step / rexi_step_adjoint (<= 64)
+ *   max_fields        largest B accepted by sh_forward / sh_inverse
+ *   fsphere, f0       fsphere = 1: the f-sphere variant (Section 4.3), a constant
+ *                     Coriolis parameter f0 (1/s) in place of 2 Omega sin(lat);
+ *                     then every (n, m) is a 3x3 system of (Phi, zeta, delta)
+ *                     (Phi_t = -Phibar delta, zeta_t = -f0 delta,
+ *                     delta_t = f0 zeta - lap Phi), whose eigenvalues are 0 and
+ *                     +-i sqrt(f0^2 + Phibar n(n+1)/a^2).  Such a plan supports
+ *                     rexi_step, rexi_step_adjoint and the transforms; the
+ *                     schedule, autotune and per-term calls return
+ *                     REXI_EUNSUPPORTED.  fsphere = 0: the rotating sphere (f0
+ *                     ignored). */
 typedef struct rexi_params {
     int T;
     int nlat, nlon;
@@ -88,6 +98,8 @@ typedef struct rexi_params {
     int normalize;
     int max_states;
     int max_fields;
+    int fsphere;
+    double f0;
 } rexi_params;
 
 /* REXI poles and weights (Section 4.1; renormalisation of Section 6.1).

@@ -151,6 +151,12 @@ struct rexi_plan {
     void* d_tiles_i = nullptr;
     int ntiles_f = 0, ntiles_i = 0;
 
+    // f-sphere variant: constant Coriolis parameter times dt, poles
+    // [N][3] (alpha, beta+, beta-), one state-sized work buffer
+    double f0dt = 0.0;
+    double2* d_fs_poles = nullptr;
+    double2* d_fs_work = nullptr;
+
     // persistent launches: one work counter per solve launch
     int* d_counters = nullptr;
     // captured step graphs: key (S, adjoint, input buffer), valid for `graph_gen`

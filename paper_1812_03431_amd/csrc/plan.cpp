@@ -23,6 +23,7 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
 hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,
                           void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s);
 hipError_t enqueue_zero(double2* p, long long n, hipStream_t s);
+hipError_t enqueue_fsphere_step(rexi_plan* pl, const void* in, void* out, int S, int adjoint, hipStream_t s);
 hipError_t enqueue_finish(rexi_plan* pl, int buf, void* u, int S, int adjoint, const MInfo* d_layout,
                           hipStream_t s);
 hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int buf, int S, hipStream_t s);
@@ -97,6 +98,8 @@ int check_params(const rexi_params* p) {
     if (!(p->h > 0) || !std::isfinite(p->h)) return fail(REXI_EINVAL, "h must be positive");
     if (p->L < 1 || p->L > 32) return fail(REXI_EINVAL, "L must be in [1, 32]");
     if (p->max_states < 1 || p->max_states > 64) return fail(REXI_EINVAL, "max_states must be in [1, 64]");
+    if (p->fsphere != 0 && p->fsphere != 1) return fail(REXI_EINVAL, "fsphere must be 0 or 1");
+    if (p->fsphere && !std::isfinite(p->f0)) return fail(REXI_EINVAL, "f0 must be finite");
     if (p->nlat != 0 || p->nlon != 0) {
         if (p->nlat < 2 || p->nlat > 4096) return fail(REXI_EINVAL, "nlat must be in [2, 4096]");
         if (p->nlon < 4 || p->nlon > 4096 || (p->nlon & (p->nlon - 1)))
@@ -395,9 +398,27 @@ using namespace rexi;
 
 namespace {
 
+// f-sphere steps: the closed-form kernel, alternating between u1 and the work
+// buffer so that the last step lands in u1.
+int run_fsphere(rexi_plan* pl, const void* u0, void* u1, int S, int nsteps, int adjoint, hipStream_t s) {
+    const size_t bytes = (size_t)S * 3 * pl->nspec * 16;
+    if (nsteps == 0) {
+        REXI_HIP(hipMemcpyAsync(u1, u0, bytes, hipMemcpyDeviceToDevice, s));
+        return REXI_OK;
+    }
+    const void* src = u0;
+    for (int k = 0; k < nsteps; ++k) {
+        void* dst = ((nsteps - 1 - k) % 2 == 0) ? u1 : (void*)pl->d_fs_work;
+        REXI_HIP(enqueue_fsphere_step(pl, src, dst, S, adjoint, s));
+        src = dst;
+    }
+    return REXI_OK;
+}
+
 int do_step(rexi_plan* pl, const void* u0, void* u1, int S, int nsteps, int adjoint, void* stream) {
     int rc = check_state_call(pl, u0, u1, S, nsteps);
     if (rc) return rc;
+    if (pl->prm.fsphere) return run_fsphere(pl, u0, u1, S, nsteps, adjoint, (hipStream_t)stream);
     std::vector<Schedule>* c = nullptr;
     rc = schedules_for(pl, S, &c);
     if (rc) return rc;
@@ -436,6 +457,8 @@ void release(rexi_plan* pl) {
     }
     dev_free(pl->d_part);
     dev_free(pl->d_acc);
+    dev_free(pl->d_fs_poles);
+    dev_free(pl->d_fs_work);
     dev_free(pl->sched_layout);
     dev_free(pl->d_slot_m);
     sh_release(pl);
@@ -542,6 +565,18 @@ int create(const rexi_params* p, rexi_plan** out) {
     for (int d = 0; d < 2 && !rc; ++d) {
         rc = dev_alloc(&pl->d_ch_var[d], (size_t)p->max_states * (pl->nslots + 2));
         if (!rc) rc = dev_alloc(&pl->d_ch_phi[d], (size_t)p->max_states * pl->nspec);
+    }
+    if (!rc && p->fsphere) {
+        pl->f0dt = p->f0 * p->dt;
+        std::vector<std::complex<double>> fp;
+        fp.reserve(3 * (size_t)N);
+        for (int k = 0; k < N; ++k) {
+            fp.push_back(pl->poles.alpha[k]);
+            fp.push_back(pl->poles.beta_plus[k]);
+            fp.push_back(pl->poles.beta_minus[k]);
+        }
+        rc = upload(&pl->d_fs_poles, to_d2(fp));
+        if (!rc) rc = dev_alloc(&pl->d_fs_work, (size_t)p->max_states * 3 * pl->nspec);
     }
     if (!rc) rc = dev_alloc(&pl->d_counters, kMaxLaunches);
     if (!rc) {
@@ -653,6 +688,7 @@ int rexi_step_adjoint(rexi_plan* plan, const void* g1, void* g0, int S, int nste
 int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* stream) {
     int rc = check_state_call(plan, u0, u1, S, 1);
     if (rc) return rc;
+    if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "the per-term form is not built for f-sphere plans");
     try {
         if ((int)plan->per_term.size() <= S) plan->per_term.resize(S + 1);
         Schedule& sc = plan->per_term[S];
@@ -680,6 +716,7 @@ int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* s
 
 int rexi_plan_set_schedule(rexi_plan* plan, int S, int index, int* count) {
     if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "f-sphere plans have no schedules");
     if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
     std::vector<Schedule>* c = nullptr;
     int rc = schedules_for(plan, S, &c);
@@ -694,6 +731,7 @@ int rexi_plan_set_schedule(rexi_plan* plan, int S, int index, int* count) {
 
 int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
     if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "f-sphere plans have no schedules");
     if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
     std::vector<Schedule>* c = nullptr;
     int rc = schedules_for(plan, S, &c);

@@ -704,6 +704,66 @@ __global__ void k_zero(double2* p, long long n) {
     if (gid < n) p[gid] = make_double2(0.0, 0.0);
 }
 
+// f-sphere variant (Section 4.3): with a constant Coriolis parameter f0 the
+// operator couples (Phi, zeta, delta) only at the same (n, m).  In energy
+// variables Phi_t = -w delta, zeta_t = -f0 delta, delta_t = f0 zeta + w Phi, so
+// with p = dt w_n and q = dt f0 the shifted system (a + dt L^) x = r has the
+// closed-form solution
+//   delta = (a r_d - q r_z - p r_P) / (a^2 + p^2 + q^2),
+//   Phi = (r_P + p delta) / a,  zeta = (r_z + q delta) / a,
+// and (a - dt L^) flips the signs of p and q.  One thread per (state, n, m)
+// sums over the poles; the adjoint uses conj(beta), conj(alpha) and
+// L^H = -L^ with the inverse scaling.  (n, m) = (0, 0): the operator is zero.
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    const double d = fma(b.r, b.r, b.i * b.i);
+    return cd{fma(a.r, b.r, a.i * b.i) / d, fma(a.i, b.r, -a.r * b.i) / d};
+}
+__device__ __forceinline__ void fsphere_solve(cd a, double p, double q, cd rP, cd rz, cd rd, cd& xP, cd& xz,
+                                              cd& xd) {
+    const cd den = cd{fma(a.r, a.r, -a.i * a.i) + p * p + q * q, 2.0 * a.r * a.i};
+    const cd num = cd{a.r * rd.r - a.i * rd.i - q * rz.r - p * rP.r, a.r * rd.i + a.i * rd.r - q * rz.i - p * rP.i};
+    xd = cdiv(num, den);
+    xP = cdiv(cd{rP.r + p * xd.r, rP.i + p * xd.i}, a);
+    xz = cdiv(cd{rz.r + q * xd.r, rz.i + q * xd.i}, a);
+}
+
+__global__ void k_fsphere_step(const double2* __restrict__ in, double2* __restrict__ out,
+                               const double2* __restrict__ poles, int N, const double* __restrict__ om,
+                               const double* __restrict__ sc, const int* __restrict__ idx_n, double qf, int S,
+                               long long nspec, int adjoint) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)S * nspec) return;
+    const int st = (int)(gid / nspec);
+    const long long i = gid - (long long)st * nspec;
+    const long long base = (long long)st * 3 * nspec + i;
+    const int n = idx_n[i];
+    const double p = n > 0 ? om[i] : 0.0, q = n > 0 ? qf : 0.0;
+    const double f = adjoint ? 1.0 / sc[i] : sc[i];  // into energy variables
+    const cd rP = ld2(in, base), rz = cscale(ld2(in, base + nspec), f), rd = cscale(ld2(in, base + 2 * nspec), f);
+    const double sg = adjoint ? -1.0 : 1.0;  // L^H = -L^
+    cd aP = mk(0, 0), az = mk(0, 0), ad = mk(0, 0);
+    for (int k = 0; k < N; ++k) {
+        cd a = ld2(poles, 3LL * k), bp = ld2(poles, 3LL * k + 1), bm = ld2(poles, 3LL * k + 2);
+        if (adjoint) {
+            a = cconj(a);
+            bp = cconj(bp);
+            bm = cconj(bm);
+        }
+        cd xP, xz, xd;
+        fsphere_solve(a, sg * p, sg * q, rP, rz, rd, xP, xz, xd);
+        aP = cfma(aP, bp, xP);
+        az = cfma(az, bp, xz);
+        ad = cfma(ad, bp, xd);
+        fsphere_solve(a, -sg * p, -sg * q, rP, rz, rd, xP, xz, xd);
+        aP = cfma(aP, bm, xP);
+        az = cfma(az, bm, xz);
+        ad = cfma(ad, bm, xd);
+    }
+    st2(out, base, aP);
+    st2(out, base + nspec, cscale(az, 1.0 / f));
+    st2(out, base + 2 * nspec, cscale(ad, 1.0 / f));
+}
+
 // LDS of one workgroup: the staged positions of the largest chain group.
 // The batched form runs kWaves waves per workgroup (sharing the staged data of
 // an item); the per-term form (ACC) one wave per chain.
@@ -846,6 +906,15 @@ hipError_t enqueue_finish(rexi_plan* pl, int buf, void* u, int S, int adjoint, c
     hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, pl->d_ch_var[buf],
                        pl->d_ch_phi[buf], (double2*)u, d_layout, pl->d_idx_n, pl->d_idx_m, pl->d_sc, adjoint, S,
                        pl->nspec, pl->nslots + 2, pl->nslots);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_fsphere_step(rexi_plan* pl, const void* in, void* out, int S, int adjoint, hipStream_t s) {
+    const long long n = (long long)S * pl->nspec;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_fsphere_step, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, (const double2*)in,
+                       (double2*)out, pl->d_fs_poles, pl->N, pl->d_om, pl->d_sc, pl->d_idx_n, pl->f0dt, S,
+                       pl->nspec, adjoint);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ class RexiParams(ctypes.Structure):
     _fields_ = [("T", c_int), ("nlat", c_int), ("nlon", c_int),
                 ("radius", c_double), ("omega", c_double), ("gravity", c_double), ("mean_depth", c_double),
                 ("dt", c_double), ("M", c_int), ("h", c_double), ("L", c_int), ("normalize", c_int),
-                ("max_states", c_int), ("max_fields", c_int)]
+                ("max_states", c_int), ("max_fields", c_int), ("fsphere", c_int), ("f0", c_double)]
 
 
 def library_path() -> str:
@@ -84,14 +84,16 @@ def rexi_coeffs(M: int, h: float, L: int = 11, normalize: bool = True):
     return tuple(out)
 
 
-def params_for(w, max_states=None, max_fields=None, normalize=True, dt=None, grid=True) -> RexiParams:
-    """rexi_params for a workload description (anything with T, nlat, nlon, dt, M, h, L, states)."""
+def params_for(w, max_states=None, max_fields=None, normalize=True, dt=None, grid=True, fsphere=None) -> RexiParams:
+    """rexi_params for a workload description (anything with T, nlat, nlon, dt, M, h, L, states).
+    ``fsphere``: None for the rotating sphere, else the constant Coriolis parameter f0 (1/s)."""
     import synth
     return RexiParams(T=w.T, nlat=w.nlat if grid else 0, nlon=w.nlon if grid else 0,
                       radius=synth.EARTH_RADIUS, omega=synth.EARTH_OMEGA, gravity=synth.GRAVITY,
                       mean_depth=synth.MEAN_DEPTH, dt=float(w.dt if dt is None else dt), M=w.M, h=w.h, L=w.L,
                       normalize=int(normalize), max_states=max_states or max(1, w.states),
-                      max_fields=max_fields or 3 * max(1, w.states))
+                      max_fields=max_fields or 3 * max(1, w.states),
+                      fsphere=0 if fsphere is None else 1, f0=0.0 if fsphere is None else float(fsphere))
 
 
 def _stream_handle(stream=None):

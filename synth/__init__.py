@@ -69,6 +69,14 @@ BUMP_WORKLOADS = {
 }
 
 
+# Numerical dispersion analysis (Section 6.3): T16, steps of at most 400 s, on
+# the f-sphere (Section 4.3).  The paper does not print f0 or M; f0 = 2 Omega
+# (the pole value) and M = 32 (h M = 6.4 covers dt sqrt(f0^2 + w_16^2) = 0.33)
+# are this build's choice.
+DISPERSION_WORKLOAD = Workload("t16_fsphere_dispersion", 16, 0, 0, 400.0, 32)
+FSPHERE_F0 = 2.0 * EARTH_OMEGA
+
+
 def nspec(T: int) -> int:
     return (T + 1) * (T + 2) // 2
 
