@@ -140,6 +140,8 @@ std::vector<MInfo> chain_layout(int T) {
 //   2 "16":      16 (L <= 256), rows
 //   3 "8/12/16": 8 (L <= 128), 12 (<= 192), 16 (<= 256), rows
 //   4 "4/8":     4 (L <= 64, rows), 4 (L <= 128, row pairs), 8 (L <= 256, row pairs)
+//   5 "fine":    8 (L <= 64), 6 (<= 96), 8 (<= 128), 10 (<= 160), 12 (<= 192),
+//                14 (<= 224), 16 (<= 256), rows: padding at most 2 elements per lane
 // Beyond 256 elements every policy uses 16 with ds_bpermute (L <= 1024).
 void tile_class(int policy, int L, int& SE, int& kind) {
     kind = 1;
@@ -160,18 +162,22 @@ void tile_class(int policy, int L, int& SE, int& kind) {
             if (L <= 192) { SE = 12; return; }
             if (L <= 256) { SE = 16; return; }
             break;
-        default:
+        case 4:
             if (L <= 64) { SE = 4; return; }
             if (L <= 128) { SE = 4; kind = 2; return; }
             if (L <= 256) { SE = 8; kind = 2; return; }
+            break;
+        default:
+            if (L <= 64) { SE = 8; return; }
+            if (L <= 256) { SE = 2 * ((L + 31) / 32); return; }  // 16 lanes x SE >= L
             break;
     }
     kind = 0;
     SE = 16;
 }
 
-const char* kPolicyName[] = {"8", "8/16", "16", "8/12/16", "4/8"};
-constexpr int kPolicies = 5;
+const char* kPolicyName[] = {"8", "8/16", "16", "8/12/16", "4/8", "fine"};
+constexpr int kPolicies = 6;
 
 // Work split of one candidate schedule.  Items are (m, chain, state, pole
 // range); the number of items per (m, chain, state) follows a cost model per
@@ -293,7 +299,7 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
     }
     std::vector<Schedule>& c = pl->sched[S];
     if (c.empty()) {
-        const long long tg[] = {1024, 2048, 4096};
+        const long long tg[] = {2048, 4096, 8192};
         for (int persistent = 0; persistent < 2; ++persistent)
             for (int policy = 0; policy < kPolicies; ++policy)
                 for (long long t : tg) {
@@ -309,7 +315,7 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
                     c.push_back(sc);
                 }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
-        pl->chosen[S] = 2;  // until autotuned: policy "8", ~4096 items
+        pl->chosen[S] = std::min<int>(5 * 3 + 1, (int)c.size() - 1);  // until autotuned: "fine", ~4096 items
     }
     *out = &c;
     return REXI_OK;

@@ -548,7 +548,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& A, int idx, double* sm
 // workgroups takes items [item0, item0 + nitems) from an atomic counter that
 // starts at zero, until none is left (every workgroup then leaves the loop).
 // Tiles of up to 8 elements per lane are held to 256 registers (two waves per
-// SIMD); larger ones use the whole register file.
+// SIMD); larger ones use the whole register file (10 would spill at 256).
 template <int SE, bool ACCUM, int KIND, int W>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(SE <= 8 ? 2 : 1)))
 k_solve(const SolveArgs A, int item0, int nitems, int* counter) {
@@ -790,8 +790,9 @@ hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, i
 
 // Compiled tilings: (elements per lane, move kind).  The per-term form needs
 // only those of the default policy.
-constexpr int kVariants[][2] = {{4, kMoveRow}, {8, kMoveRow}, {12, kMoveRow}, {16, kMoveRow},
-                                {4, kMovePair}, {8, kMovePair}, {16, kMoveBperm}};
+constexpr int kVariants[][2] = {{4, kMoveRow},  {6, kMoveRow},  {8, kMoveRow},  {10, kMoveRow},
+                                {12, kMoveRow}, {14, kMoveRow}, {16, kMoveRow}, {4, kMovePair},
+                                {8, kMovePair}, {16, kMoveBperm}};
 constexpr int kPerTermVariants[][2] = {{8, kMoveRow}, {8, kMovePair}, {16, kMoveBperm}};
 
 template <bool ACC>
@@ -806,7 +807,10 @@ hipError_t launch_solve(const Launch& L, const SolveArgs& a, int* counter, hipSt
     REXI_CASE(16, kMoveBperm);
     if constexpr (!ACC) {
         REXI_CASE(4, kMoveRow);
+        REXI_CASE(6, kMoveRow);
+        REXI_CASE(10, kMoveRow);
         REXI_CASE(12, kMoveRow);
+        REXI_CASE(14, kMoveRow);
         REXI_CASE(16, kMoveRow);
         REXI_CASE(4, kMovePair);
     }
