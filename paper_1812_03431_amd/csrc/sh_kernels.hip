@@ -136,12 +136,14 @@ constexpr int kPD = kPhase + 1;  // LDS row length of a generated tile (odd: spr
 constexpr int kLatBlock = 64;    // latitudes generated per forward block
 
 // Forward work: one run of order m.  Inverse work: latitude tiles [t0, t1) of
-// order m (one wave each); run0 = first restart row of m.
+// the orders m and m2 = T - m (one wave each, m2 = -1 when m = T - m); run0,
+// run2 = first restart rows of the two orders.
 struct LegRun {
     int m, n0, row, pad;
 };
 struct LegWork {
     int m, t0, t1, run0;
+    int m2, run2;  // second order of the workgroup (T - m), or -1
 };
 
 // Forward: out[b][idx(m, n)] = sum_{j<H} P_n^m(mu_j) w_j (F_j +- F_j'), + for
@@ -170,6 +172,7 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
     double* O = E + H * C;                            // [H][C]
     double* Pt = O + H * C;                           // [kLatBlock][kPD]
     double2* st = reinterpret_cast<double2*>(Pt + kLatBlock * kPD);  // [H]: (P_{n-1}, P_n)
+    double* xs = reinterpret_cast<double*>(st + H);                  // [H]: mu_j
     // coefficients of degree n0 + k: a separate LDS object, so that the
     // compiler sees they cannot alias the generated tile
     __shared__ double2 cf[kRun + 1];
@@ -195,8 +198,10 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
             }
         }
     }
-    for (int j = tid; j < H; j += blockDim.x)
+    for (int j = tid; j < H; j += blockDim.x) {
         st[j] = make_double2(restart[((long long)rn.row * 2) * H + j], restart[((long long)rn.row * 2 + 1) * H + j]);
+        xs[j] = mu[j];
+    }
     for (int k = tid; k <= kRun; k += blockDim.x)
         cf[k] = (k >= 1 && n0 + k <= T) ? coef[so + (n0 + k - m)] : make_double2(0.0, 0.0);
     const int nend = min(T, n0 + kRun - 1);
@@ -216,7 +221,7 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
             __syncthreads();  // staging done / previous block consumed
             if (tid < nl) {
                 const int j = lb + tid;
-                const double x = mu[j];
+                const double x = xs[j];
                 double2 pc = st[j];
                 const int k0 = ph - n0;  // cf index of degree ph is k0; step n -> n+1 uses k + 1
 #pragma unroll
@@ -228,15 +233,17 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
                 st[j] = pc;
             }
             __syncthreads();
-            if (has_tile) {
-                // the block's 16 k-steps: all fragment reads first, then the MFMAs
+            {
+                // the block's 16 k-steps: all fragment reads first, then the MFMAs.
+                // A wave without a tile multiplies zeros; no branch around the
+                // MFMAs keeps the accumulators in place.
                 constexpr int kSteps = kLatBlock / 4;
                 double av[kSteps], bv[kSteps];
 #pragma unroll
                 for (int q = 0; q < kSteps; ++q) {
                     const int lat = (q >> 2) * 16 + 4 * kq + (q & 3);  // < kLatBlock
                     const bool lok = lat < nl;
-                    av[q] = lok ? Pt[lat * kPD + 2 * row + r] : 0.0;
+                    av[q] = (lok && has_tile) ? Pt[lat * kPD + 2 * row + r] : 0.0;
                     bv[q] = (lok && cok) ? Bm[(lb + min(lat, nl - 1)) * C + col] : 0.0;
                 }
 #pragma unroll
@@ -259,99 +266,84 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
 }
 
 // Inverse: Fw[m][j] = Fe + Fo, Fw[m][j'] = Fe - Fo with Fe / Fo the sums of
-// P_n^m(mu_j) S_n over n - m even / odd.  The spectral block of m, Sm [L][C],
-// is staged in LDS; each wave owns 16 latitudes.  Lanes (i = lane & 15,
-// kq = lane >> 4) run the recurrence of latitude i in registers (the four kq
-// lanes alike) and keep what their MFMA fragment needs: per k-step of 8
-// degrees base .. base + 7, A_even = P_{base + 2 kq}, A_odd = P_{base + 2 kq + 1}.
-__global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restrict__ work,
-                                                          const double* __restrict__ restart,
-                                                          const double2* __restrict__ coef,
-                                                          const double* __restrict__ mu,
-                                                          const double* __restrict__ spec,
-                                                          double* __restrict__ Fw, int T, int nlat, int H, int Cs,
-                                                          int c_off, int C) {
-    extern __shared__ double lds[];
-    const LegWork wk = work[blockIdx.x];
-    const int m = wk.m;
-    const long long so = spec_offset(T, m);
-    const long long ns = nspec_of(T);
-    const int L = T + 1 - m;
-    double* Sm = lds;  // [L][C]
-    constexpr int kU = 8;  // loads in flight per thread while staging
-    for (int i0 = 0; i0 < L * C; i0 += kU * 256) {
-        double v[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int idx = i0 + u * 256 + threadIdx.x;
-            const bool ok = idx < L * C;
-            const int d = ok ? idx / C : 0, c = ok ? idx - d * C : 0;
-            v[u] = ok ? spec[((long long)((c_off + c) >> 1) * ns + so + d) * 2 + ((c_off + c) & 1)] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int idx = i0 + u * 256 + threadIdx.x;
-            if (idx < L * C) Sm[idx] = v[u];
-        }
-    }
-    // recurrence coefficients of degree m + k, k < L + 8 (zero beyond T)
-    double2* cf = reinterpret_cast<double2*>(Sm + L * C);
-    for (int k = threadIdx.x; k < L + 8; k += blockDim.x)
-        cf[k] = (k >= 1 && k < L) ? coef[so + k] : make_double2(0.0, 0.0);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int t = wk.t0 + wave;
-    if (t >= wk.t1) return;  // no latitude tile for this wave (no barrier follows)
+// P_n^m(mu_j) S_n over n - m even / odd.  A workgroup takes the orders m and
+// T - m together (their lengths add up to T + 2, which evens out the work),
+// stages both spectral blocks Sm [L][C] and coefficient columns in LDS, and
+// each wave owns 16 latitudes.  Lanes (i = lane & 15, kq = lane >> 4) run the
+// recurrence of latitude i in registers (the four kq lanes alike) and keep
+// what their MFMA fragment needs: per k-step of 8 degrees base .. base + 7,
+// A_even = P_{base + 2 kq}, A_odd = P_{base + 2 kq + 1}.  The coefficients and
+// B fragments of the next k-step are read while the current one is worked on.
+struct InvOrder {
+    int m, run0;
+    const double* Sm;   // [L][C] in LDS
+    const double2* cf;  // [L + 16] in LDS: coefficients of degree m + k (zero outside 1 <= k < L)
+};
+
+template <int NCT>
+__device__ __forceinline__ void inverse_order(const InvOrder& od, const double* __restrict__ restart,
+                                              double* __restrict__ Fw, int T, int nlat, int H, int Cs, int c_off,
+                                              int C, int t, int lane, double x, bool jok) {
+    const int m = od.m, L = T + 1 - m;
     const int i = lane & 15, kq = lane >> 4;
     const int j = t * 16 + i;
-    const bool jok = j < H;
-    const double x = jok ? mu[j] : 0.0;
-    const int nct = (C + 15) / 16;  // <= 2
+    constexpr int nct = NCT;  // column tiles (C <= 16 NCT)
+    const double* Sm = od.Sm;
+    const double2* cf = od.cf;
+    auto loadB = [&](int kb, double* b) {  // be, bo of column tiles 0 and 1
+        const int de = kb + 2 * kq, dodd = de + 1;
+        const int c0 = i, c1 = 16 + i;
+        const int e_r = min(de, L - 1), o_r = min(dodd, L - 1);
+        b[0] = (de < L && c0 < C) ? Sm[e_r * C + min(c0, C - 1)] : 0.0;
+        b[1] = (dodd < L && c0 < C) ? Sm[o_r * C + min(c0, C - 1)] : 0.0;
+        b[2] = (de < L && c1 < C) ? Sm[e_r * C + min(c1, C - 1)] : 0.0;
+        b[3] = (dodd < L && c1 < C) ? Sm[o_r * C + min(c1, C - 1)] : 0.0;
+    };
     v4d ae0 = {0.0, 0.0, 0.0, 0.0}, ao0 = ae0, ae1 = ae0, ao1 = ae0;
-    // restart rows of run 0, and of run rr + 1 read while run rr is worked on
-    double pv_n = jok ? restart[((long long)wk.run0 * 2) * H + j] : 0.0;
-    double cu_n = jok ? restart[((long long)wk.run0 * 2 + 1) * H + j] : 0.0;
-    for (int rr = 0; m + kRun * rr <= T; ++rr) {
-        const int n0 = m + kRun * rr;
-        double pv = pv_n, cu = cu_n;
-        if (m + kRun * (rr + 1) <= T && jok) {
-            const int row = wk.run0 + rr + 1;
-            pv_n = restart[((long long)row * 2) * H + j];
-            cu_n = restart[((long long)row * 2 + 1) * H + j];
-        }
-        const int nend = min(T, n0 + kRun - 1);
-        for (int base = n0; base <= nend; base += 8) {
-            double a_e = 0.0, a_o = 0.0;
-            const int kb = base - m;  // cf index of degree base
+    double pv = 0.0, cu = 0.0;
+    double pv_n = jok ? restart[((long long)od.run0 * 2) * H + j] : 0.0;
+    double cu_n = jok ? restart[((long long)od.run0 * 2 + 1) * H + j] : 0.0;
+    double2 cfv[8];
+    double bv[4];
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const double v = (base + d <= nend) ? cu : 0.0;
-                if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? v : a_e;
-                else a_o = (kq == (d >> 1)) ? v : a_o;
-                const double2 ab = cf[kb + d + 1];
-                const double nx = fma(ab.x * x, cu, -ab.y * pv);
-                pv = cu;
-                cu = nx;
-            }
-            const int de = base - m + 2 * kq, dodd = de + 1;
-            const bool eok = de < L, ook = dodd < L;
-            {
-                const int col = i;
-                const bool cok = col < C;
-                const double be = (eok && cok) ? Sm[de * C + col] : 0.0;
-                const double bo = (ook && cok) ? Sm[dodd * C + col] : 0.0;
-                ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, be, ae0, 0, 0, 0);
-                ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bo, ao0, 0, 0, 0);
-            }
-            if (nct > 1) {
-                const int col = 16 + i;
-                const bool cok = col < C;
-                const double be = (eok && cok) ? Sm[de * C + col] : 0.0;
-                const double bo = (ook && cok) ? Sm[dodd * C + col] : 0.0;
-                ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, be, ae1, 0, 0, 0);
-                ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bo, ao1, 0, 0, 0);
+    for (int d = 0; d < 8; ++d) cfv[d] = cf[d + 1];
+    loadB(0, bv);
+    for (int kb = 0; kb < L; kb += 8) {
+        double2 cfn[8];
+        double bn[4];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) cfn[d] = cf[kb + 8 + d + 1];  // < L + 16
+        loadB(kb + 8, bn);
+        __builtin_amdgcn_sched_barrier(0);  // keep the next k-step's reads ahead of this one's work
+        if ((kb & (kRun - 1)) == 0) {       // start of a run: exact restart values
+            pv = pv_n;
+            cu = cu_n;
+            if (kb + kRun < L && jok) {
+                const int row = od.run0 + kb / kRun + 1;
+                pv_n = restart[((long long)row * 2) * H + j];
+                cu_n = restart[((long long)row * 2 + 1) * H + j];
             }
         }
+        double a_e = 0.0, a_o = 0.0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const double v = (kb + d < L) ? cu : 0.0;
+            if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? v : a_e;
+            else a_o = (kq == (d >> 1)) ? v : a_o;
+            const double nx = fma(cfv[d].x * x, cu, -cfv[d].y * pv);
+            pv = cu;
+            cu = nx;
+        }
+        ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, bv[0], ae0, 0, 0, 0);
+        ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bv[1], ao0, 0, 0, 0);
+        if constexpr (NCT > 1) {
+            ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, bv[2], ae1, 0, 0, 0);
+            ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bv[3], ao1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) cfv[d] = cfn[d];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q] = bn[q];
     }
     // accumulator register q of lane l holds D[4 q + l/16][l % 16]: latitude
     // row 4 q + kq of the tile, column l % 16 of the column tile
@@ -371,11 +363,76 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     }
 }
 
+// Stage the spectral block of order m ([L][C], columns c_off..) and its
+// coefficient column ([L + 16]) into LDS; every thread issues its loads first.
+__device__ __forceinline__ void stage_order(int m, int T, int C, int c_off, const double* __restrict__ spec,
+                                            const double2* __restrict__ coef, double* Sm, double2* cf) {
+    const long long so = spec_offset(T, m);
+    const long long ns = nspec_of(T);
+    const int L = T + 1 - m;
+    constexpr int kU = 8;
+    for (int i0 = 0; i0 < L * C; i0 += kU * 256) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int idx = i0 + u * 256 + threadIdx.x;
+            const bool ok = idx < L * C;
+            const int d = ok ? idx / C : 0, c = ok ? idx - d * C : 0;
+            v[u] = ok ? spec[((long long)((c_off + c) >> 1) * ns + so + d) * 2 + ((c_off + c) & 1)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int idx = i0 + u * 256 + threadIdx.x;
+            if (idx < L * C) Sm[idx] = v[u];
+        }
+    }
+    for (int k = threadIdx.x; k < L + 16; k += blockDim.x)
+        cf[k] = (k >= 1 && k < L) ? coef[so + k] : make_double2(0.0, 0.0);
+}
+
+template <int NCT>
+__global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restrict__ work,
+                                                          const double* __restrict__ restart,
+                                                          const double2* __restrict__ coef,
+                                                          const double* __restrict__ mu,
+                                                          const double* __restrict__ spec,
+                                                          double* __restrict__ Fw, int T, int nlat, int H, int Cs,
+                                                          int c_off, int C) {
+    extern __shared__ double lds[];
+    const LegWork wk = work[blockIdx.x];
+    const int L0 = T + 1 - wk.m;
+    InvOrder o0, o1;
+    o0.m = wk.m;
+    o0.run0 = wk.run0;
+    o0.Sm = lds;
+    o0.cf = reinterpret_cast<const double2*>(lds + L0 * C);  // L0 * C is even (C is)
+    stage_order(o0.m, T, C, c_off, spec, coef, lds, reinterpret_cast<double2*>(lds + L0 * C));
+    if (wk.m2 >= 0) {
+        double* p = lds + L0 * C + 2 * (L0 + 16);
+        const int L1 = T + 1 - wk.m2;
+        o1.m = wk.m2;
+        o1.run0 = wk.run2;
+        o1.Sm = p;
+        o1.cf = reinterpret_cast<const double2*>(p + L1 * C);
+        stage_order(o1.m, T, C, c_off, spec, coef, p, reinterpret_cast<double2*>(p + L1 * C));
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = wk.t0 + wave;
+    if (t >= wk.t1) return;  // no latitude tile for this wave (no barrier follows)
+    const int j = t * 16 + (lane & 15);
+    const bool jok = j < H;
+    const double x = jok ? mu[j] : 0.0;
+    inverse_order<NCT>(o0, restart, Fw, T, nlat, H, Cs, c_off, C, t, lane, x, jok);
+    if (wk.m2 >= 0) inverse_order<NCT>(o1, restart, Fw, T, nlat, H, Cs, c_off, C, t, lane, x, jok);
+}
+
 constexpr size_t kLdsBytes = 96 * 1024;  // LDS per workgroup used by the Legendre kernels
 
 // LDS of the forward kernel besides E and O: generated tile, state, coefficients.
 size_t forward_fixed_lds(int H) {
-    return sizeof(double) * kLatBlock * kPD + sizeof(double2) * (size_t)H + sizeof(double2) * (kRun + 1);
+    return sizeof(double) * kLatBlock * kPD + (sizeof(double2) + sizeof(double)) * (size_t)H +
+           sizeof(double2) * (kRun + 1);
 }
 // Largest column chunk (even, <= 32) whose LDS fits kLdsBytes.
 int forward_chunk(int H, int C) {
@@ -384,9 +441,14 @@ int forward_chunk(int H, int C) {
     const int cc = (int)((kLdsBytes - pt) / per_col) & ~1;
     return std::max(2, std::min(std::min(C, 32), cc));
 }
+// Inverse LDS: both orders' blocks (lengths T + 1 - m and m + 1, together
+// T + 2) and coefficient columns.
+size_t inverse_lds(int T, int w) {
+    return sizeof(double) * (size_t)(T + 2) * w + sizeof(double2) * (size_t)(T + 2 + 32);
+}
 int inverse_chunk(int T, int C) {
-    const size_t cfb = sizeof(double2) * (T + 1 + 8);
-    const int cc = (int)((kLdsBytes - cfb) / (sizeof(double) * (T + 1))) & ~1;
+    const size_t cfb = sizeof(double2) * (T + 2 + 32);
+    const int cc = (int)((kLdsBytes - cfb) / (sizeof(double) * (T + 2))) & ~1;
     return std::max(2, std::min(std::min(C, 32), cc));
 }
 
@@ -414,14 +476,17 @@ int sh_setup(rexi_plan* pl) {
         tw[k] = make_double2((double)cosl(a), (double)sinl(a));
     }
     // forward: one workgroup per run, longest orders first (they come first);
-    // inverse: four latitude tiles (one per wave) of one order per workgroup
+    // inverse: four latitude tiles (one per wave) of one order
     std::vector<LegRun> tf;
     std::vector<LegWork> ti;
     const int nl = (H + 15) / 16;
     for (int m = 0; m <= T; ++m) {
         for (int r = 0; m + kRun * r <= T; ++r) tf.push_back(LegRun{m, m + kRun * r, run_base[m] + r, 0});
-        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m]});
     }
+    // one order per workgroup: pairing m with T - m evens the work per wave
+    // but halves the waves in flight, which measured slower (30 vs 26 us at T256)
+    for (int m = 0; m <= T; ++m)
+        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m], -1, 0});
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes ? bytes : 1);
         if (e != hipSuccess) return fail(REXI_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
@@ -451,7 +516,9 @@ int sh_setup(rexi_plan* pl) {
     REXI_HIP(hipFuncSetAttribute((const void*)k_fft_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
     REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_forward, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kLdsBytes));
-    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kLdsBytes));
+    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kLdsBytes));
     return REXI_OK;
 }
@@ -507,10 +574,15 @@ int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStr
         const int cc = inverse_chunk(pl->T, C);
         for (int c0 = 0; c0 < C; c0 += cc) {
             const int w = std::min(cc, C - c0);
-            const size_t li = sizeof(double) * (size_t)(pl->T + 1) * w + sizeof(double2) * (pl->T + 1 + 8);
-            hipLaunchKernelGGL(k_legendre_inverse, dim3(pl->ntiles_i), dim3(256), li, s,
-                               (const LegWork*)pl->d_tiles_i, pl->d_restart, coef, pl->d_mu, (const double*)in,
-                               pl->d_four, pl->T, pl->nlat, H, C, c0, w);
+            const size_t li = inverse_lds(pl->T, w);
+            if (w > 16)
+                hipLaunchKernelGGL(k_legendre_inverse<2>, dim3(pl->ntiles_i), dim3(256), li, s,
+                                   (const LegWork*)pl->d_tiles_i, pl->d_restart, coef, pl->d_mu, (const double*)in,
+                                   pl->d_four, pl->T, pl->nlat, H, C, c0, w);
+            else
+                hipLaunchKernelGGL(k_legendre_inverse<1>, dim3(pl->ntiles_i), dim3(256), li, s,
+                                   (const LegWork*)pl->d_tiles_i, pl->d_restart, coef, pl->d_mu, (const double*)in,
+                                   pl->d_four, pl->T, pl->nlat, H, C, c0, w);
             REXI_HIP(hipGetLastError());
         }
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_INV, s));
