@@ -89,6 +89,34 @@ def test_step_long_chains_every_schedule(torch_dev, T, S, M, dt, orders):
     assert_parity(got[:, :, mask], want[:, :, mask], what=f"T{T} per-term")
 
 
+def test_step_chains_beyond_256_elements(torch_dev):
+    # T400: chains of up to 400 elements run 16 elements per lane over 32
+    # lanes with ds_bpermute moves, under every policy
+    T, S, M, dt = 400, 1, 16, 120.0
+    orders = [0, 1, 143, 144, 145, 399, 400]
+    w = synth.Workload("vlong", T=T, nlat=0, nlon=0, dt=dt, M=M, states=S)
+    u0 = synth.random_state(T, S, 400)
+    mask = block_mask(T, orders)
+    want = _oracle_step(u0, w, orders=orders)
+    want_a = _oracle_step(u0, w, adjoint=True, orders=orders)
+    plan = _plan(w, grid=False)
+    for i in range(plan.schedule_count(S)):
+        plan.set_schedule(S, i)
+        print(f"  schedule {i}", flush=True)
+        got = plan.step(_gpu(u0, torch_dev)).cpu().numpy()
+        assert_parity(got[:, :, mask], want[:, :, mask], what=f"T{T} schedule {i}")
+        got_a = plan.step_adjoint(_gpu(u0, torch_dev)).cpu().numpy()
+        assert_parity(got_a[:, :, mask], want_a[:, :, mask], what=f"T{T} adjoint schedule {i}")
+
+
+def test_zero_steps_copy_the_state(torch_dev):
+    w = synth.Workload("zero", T=20, nlat=0, nlon=0, dt=3600.0, M=16, states=2)
+    plan = _plan(w, grid=False)
+    u0 = _gpu(synth.random_state(w.T, 2, 5), torch_dev)
+    assert np.array_equal(plan.step(u0, nsteps=0).cpu().numpy(), u0.cpu().numpy())
+    assert np.array_equal(plan.step_adjoint(u0, nsteps=0).cpu().numpy(), u0.cpu().numpy())
+
+
 def test_multistep_and_adjoint(torch_dev):
     w = synth.Workload("ms", T=20, nlat=0, nlon=0, dt=3600.0, M=64, states=2)
     u0 = synth.random_state(w.T, 2, 7)
