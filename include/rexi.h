@@ -185,6 +185,13 @@ int rexi_plan_set_schedule(rexi_plan *plan, int S, int index, int *count);
  * kernels one by one instead.  Results are identical either way. */
 int rexi_plan_set_graphs(rexi_plan *plan, int enable);
 
+/* Tile-class launches.  A step launches one solve kernel per tile class; by
+ * default they run concurrently on side streams of the plan (default
+ * priority), forked from and joined back into the caller's stream, so that
+ * the tail of one class overlaps the others.  enable = 0 launches them one
+ * after another on the caller's stream.  Results are identical either way. */
+int rexi_plan_set_streams(rexi_plan *plan, int enable);
+
 /* Kernel timing for measurement.  rexi_plan_set_timing(plan, 1) makes the plan
  * bracket every later launch of the timed kernels with a HIP event pair on the
  * launch stream (steps then run as individual launches, not graphs); 0 stops

@@ -170,6 +170,11 @@ struct rexi_plan {
     long long graph_gen = 0;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
+    // concurrent tile-class launches: side streams, fork and join events
+    bool concurrent = true;
+    hipStream_t side[rexi::kMaxLaunches] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[rexi::kMaxLaunches] = {};
 
     // measurement: event pairs around timed launches, per kernel kind
     bool timing = false;

@@ -447,6 +447,14 @@ void release(rexi_plan* pl) {
     dev_free(pl->d_counters);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     pl->cap_stream = nullptr;
+    for (int c = 0; c < kMaxLaunches; ++c) {
+        if (pl->side[c]) (void)hipStreamDestroy(pl->side[c]);
+        if (pl->join_ev[c]) (void)hipEventDestroy(pl->join_ev[c]);
+        pl->side[c] = nullptr;
+        pl->join_ev[c] = nullptr;
+    }
+    if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
+    pl->fork_ev = nullptr;
     for (auto& c : pl->sched)
         for (auto& s : c) free_schedule(s);
     for (auto& s : pl->per_term) free_schedule(s);
@@ -592,6 +600,15 @@ int create(const rexi_params* p, rexi_plan** out) {
     if (!rc) {
         hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) rc = hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    for (int c = 0; c < kMaxLaunches && !rc; ++c) {
+        hipError_t e = hipStreamCreateWithFlags(&pl->side[c], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join_ev[c], hipEventDisableTiming);
+        if (e != hipSuccess) rc = hip_fail(e, "side stream / event");
+    }
+    if (!rc) {
+        hipError_t e = hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming);
+        if (e != hipSuccess) rc = hip_fail(e, "hipEventCreateWithFlags");
     }
     if (!rc && p->nlat > 0) rc = sh_setup(pl);
     if (rc) {
@@ -781,6 +798,14 @@ int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
     if (plan->chosen[S] != best) drop_graphs(plan);
     plan->chosen[S] = best;
     if (chosen) *chosen = best;
+    return REXI_OK;
+}
+
+int rexi_plan_set_streams(rexi_plan* plan, int enable) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    const bool on = enable != 0;
+    if (on != plan->concurrent) drop_graphs(plan);
+    plan->concurrent = on;
     return REXI_OK;
 }
 

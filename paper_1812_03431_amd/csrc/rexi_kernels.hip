@@ -865,11 +865,25 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    for (size_t c = 0; c < sc.launches.size(); ++c) {
-        hipError_t e = launch_solve<false>(sc.launches[c], a, sc.persistent ? pl->d_counters + c : nullptr, s);
-        if (e != hipSuccess) return e;
+    const int nl = (int)sc.launches.size();
+    if (!pl->concurrent || nl < 2) {
+        for (int c = 0; c < nl; ++c) {
+            hipError_t e = launch_solve<false>(sc.launches[c], a, sc.persistent ? pl->d_counters + c : nullptr, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
-    return hipSuccess;
+    // fork: every class on its own side stream after the work already on s;
+    // join: s waits for all of them (each class writes its own partials)
+    hipError_t e = hipEventRecord(pl->fork_ev, s);
+    for (int c = 0; c < nl && e == hipSuccess; ++c) {
+        e = hipStreamWaitEvent(pl->side[c], pl->fork_ev, 0);
+        if (e == hipSuccess)
+            e = launch_solve<false>(sc.launches[c], a, sc.persistent ? pl->d_counters + c : nullptr, pl->side[c]);
+        if (e == hipSuccess) e = hipEventRecord(pl->join_ev[c], pl->side[c]);
+    }
+    for (int c = 0; c < nl && e == hipSuccess; ++c) e = hipStreamWaitEvent(s, pl->join_ev[c], 0);
+    return e;
 }
 
 hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,

@@ -55,6 +55,7 @@ def load_library():
         "rexi_plan_set_schedule": [P, c_int, c_int, POINTER(c_int)],
         "rexi_plan_set_timing": [P, c_int],
         "rexi_plan_set_graphs": [P, c_int],
+        "rexi_plan_set_streams": [P, c_int],
         "rexi_plan_kernel_time": [P, c_int, POINTER(c_double), POINTER(c_longlong)],
     }
     for name, args in sigs.items():
@@ -211,6 +212,10 @@ class Plan:
 
     def set_graphs(self, enable: bool):
         _check(self._lib.rexi_plan_set_graphs(self._h, int(enable)), "rexi_plan_set_graphs")
+
+    def set_streams(self, enable: bool):
+        """Tile-class launches concurrent on side streams (True, default) or serial."""
+        _check(self._lib.rexi_plan_set_streams(self._h, int(enable)), "rexi_plan_set_streams")
 
     def set_timing(self, enable: bool):
         _check(self._lib.rexi_plan_set_timing(self._h, int(enable)), "rexi_plan_set_timing")
