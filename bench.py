@@ -76,8 +76,10 @@ def load_traffic(digest):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(w, budget_s):
-    """The oracle, as is, on a bounded sample of the workload's orders."""
+def cpu_baseline(w, budget_s, gpu_fwd=None, gpu_adj=None):
+    """The oracle, as is, on a bounded sample of the workload's orders.  When
+    the GPU's step and adjoint of the same states are given, the oracle's
+    results on the sampled orders double as an accuracy check of them."""
     import numpy as np
     import synth
     from oracle import coeffs, rexi as orexi
@@ -89,19 +91,58 @@ def cpu_baseline(w, budget_s):
     orders = list(range(0, w.T + 1, stride))
     t0, c0 = time.perf_counter(), time.process_time()
     done = []
+    fwd = np.zeros_like(u0)
+    adj = np.zeros_like(u0)
     for m in orders:
-        orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, orders=[m])
-        orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, orders=[m], adjoint=True)
+        fwd += orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, orders=[m])
+        adj += orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, orders=[m], adjoint=True)
         done.append(m)
         if time.perf_counter() - t0 > budget_s:
             break
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     blocks = 2 * N * len(done)
-    return {"value": blocks / wall, "unit": "blocks/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
-            "sample": f"one forward and one adjoint step of {w.states} states for orders m = "
-                      f"{done[0]}..{done[-1]} step {stride} ({len(done)} of {w.T + 1} orders, mean chain "
-                      f"length {np.mean([w.T + 1 - m for m in done]):.0f}); {wall:.1f} s wall"}
+    out = {"value": blocks / wall, "unit": "blocks/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
+           "sample": f"one forward and one adjoint step of {w.states} states for orders m = "
+                     f"{done[0]}..{done[-1]} step {stride} ({len(done)} of {w.T + 1} orders, mean chain "
+                     f"length {np.mean([w.T + 1 - m for m in done]):.0f}); {wall:.1f} s wall"}
+    if gpu_fwd is not None:
+        mask = np.zeros(u0.shape[-1], dtype=bool)
+        for m in done:
+            o = m * (w.T + 1) - m * (m - 1) // 2
+            mask[o:o + w.T + 1 - m] = True
+
+        def worst(got, want):
+            return max(float(np.linalg.norm(got[s, v, mask] - want[s, v, mask]) / np.linalg.norm(want[s, v, mask]))
+                       for s in range(u0.shape[0]) for v in range(3))
+        out["gpu_parity"] = {"orders": f"{done[0]}..{done[-1]} step {stride}",
+                             "max_rel_l2_forward": worst(gpu_fwd, fwd), "max_rel_l2_adjoint": worst(gpu_adj, adj),
+                             "per": "state and variable", "bound": 1e-10}
+    return out
+
+
+def graph_replay_medians(plan, u, reps=25):
+    """Median of `reps` graph replays of one forward and one adjoint step
+    (HIP events around each replay on the launch stream)."""
+    import torch
+    plan.set_timing(False)
+    plan.set_graphs(True)
+    out = {}
+    for name, fn in (("forward_ms", plan.step), ("adjoint_ms", plan.step_adjoint)):
+        fn(u)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn(u)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        out[name] = sorted(times)[len(times) // 2]
+    out["replays"] = reps
+    out["note"] = "each replay includes the layout conversions into and out of the chain layout"
+    return out
 
 
 def bump_runs(rexi, synth, torch, dev, reps=3):
@@ -297,8 +338,12 @@ def main():
     if not args.no_bumps:
         rec["bumps"] = bump_runs(rexi, synth, torch, dev)
         rec["dispersion"] = dispersion_run(rexi, synth, torch, dev)
+    rec["graph_replay_median"] = graph_replay_medians(plan, u)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        us = torch.from_numpy(synth.random_state(T, S, 0)).to(dev)
+        gf = plan.step(us).cpu().numpy()
+        ga = plan.step_adjoint(us).cpu().numpy()
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, gf, ga)
     print(json.dumps(rec), flush=True)
 
 
