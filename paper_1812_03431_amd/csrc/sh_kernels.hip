@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
 // recurrence P_n = a_n mu P_{n-1} - b_n P_{n-2}, restarted every kRun degrees
 // from exact host values, which keeps the FP64 recurrence error at a few ulp.
 constexpr int kRun = 64;         // degrees per restart run
+constexpr int kFwdRun = 128;     // degrees per forward workgroup (a multiple of kRun)
 constexpr int kPhase = 32;       // degrees generated per forward phase (two 16-row parity tiles)
 constexpr int kPD = kPhase + 1;  // LDS row length of a generated tile (odd: spreads banks)
 constexpr int kLatBlock = 64;    // latitudes generated per forward block
@@ -147,7 +148,7 @@ struct LegWork {
 };
 
 // Forward: out[b][idx(m, n)] = sum_{j<H} P_n^m(mu_j) w_j (F_j +- F_j'), + for
-// n - m even, - for odd, over the degrees n0 .. n0 + kRun - 1 of one run.
+// n - m even, - for odd, over the degrees n0 .. n0 + kFwdRun - 1 of one run.
 // Staged once in LDS: the weighted even/odd Fourier blocks E, O [H][C], the
 // run's recurrence coefficients (zero beyond T) and the recurrence state of
 // every latitude.  Per phase of 32 degrees and block of kLatBlock latitudes,
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
     double* xs = reinterpret_cast<double*>(st + H);                  // [H]: mu_j
     // coefficients of degree n0 + k: a separate LDS object, so that the
     // compiler sees they cannot alias the generated tile
-    __shared__ double2 cf[kRun + 1];
+    __shared__ double2 cf[kFwdRun + 1];
     // staging: every thread issues kU loads before its stores (one latency)
     constexpr int kU = 8;
     for (int i0 = 0; i0 < H * C; i0 += kU * 256) {
@@ -202,9 +203,9 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
         st[j] = make_double2(restart[((long long)rn.row * 2) * H + j], restart[((long long)rn.row * 2 + 1) * H + j]);
         xs[j] = mu[j];
     }
-    for (int k = tid; k <= kRun; k += blockDim.x)
+    for (int k = tid; k <= kFwdRun; k += blockDim.x)
         cf[k] = (k >= 1 && n0 + k <= T) ? coef[so + (n0 + k - m)] : make_double2(0.0, 0.0);
-    const int nend = min(T, n0 + kRun - 1);
+    const int nend = min(T, n0 + kFwdRun - 1);
     const int lane = tid & 63, wave = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int nct = (C + 15) / 16;       // column tiles (<= 2)
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
 #pragma unroll
                 for (int d = 0; d < kPhase; ++d) {
                     Pt[tid * kPD + d] = (ph + d <= nend) ? pc.y : 0.0;
-                    const double2 ab = cf[min(k0 + d + 1, kRun)];
+                    const double2 ab = cf[min(k0 + d + 1, kFwdRun)];
                     pc = make_double2(pc.y, fma(ab.x * x, pc.y, -ab.y * pc.x));
                 }
                 st[j] = pc;
@@ -364,26 +365,34 @@ __device__ __forceinline__ void inverse_order(const InvOrder& od, const double* 
 }
 
 // Stage the spectral block of order m ([L][C], columns c_off..) and its
-// coefficient column ([L + 16]) into LDS; every thread issues its loads first.
+// coefficient column ([L + 16]) into LDS.  The coefficients of one field and
+// order are contiguous in memory (2L doubles), so threads walk them field by
+// field (coalesced reads) and transpose into [d][c] in LDS; every thread
+// issues its loads before its stores.
 __device__ __forceinline__ void stage_order(int m, int T, int C, int c_off, const double* __restrict__ spec,
                                             const double2* __restrict__ coef, double* Sm, double2* cf) {
     const long long so = spec_offset(T, m);
     const long long ns = nspec_of(T);
     const int L = T + 1 - m;
+    const int L2 = 2 * L;  // doubles per field (re, im interleaved)
+    const int nb = C / 2;  // fields of this column chunk (C even, c_off even)
     constexpr int kU = 8;
-    for (int i0 = 0; i0 < L * C; i0 += kU * 256) {
+    for (int i0 = 0; i0 < nb * L2; i0 += kU * 256) {
         double v[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int idx = i0 + u * 256 + threadIdx.x;
-            const bool ok = idx < L * C;
-            const int d = ok ? idx / C : 0, c = ok ? idx - d * C : 0;
-            v[u] = ok ? spec[((long long)((c_off + c) >> 1) * ns + so + d) * 2 + ((c_off + c) & 1)] : 0.0;
+            const bool ok = idx < nb * L2;
+            const int f = ok ? idx / L2 : 0, k = ok ? idx - f * L2 : 0;
+            v[u] = ok ? spec[((long long)((c_off >> 1) + f) * ns + so) * 2 + k] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int idx = i0 + u * 256 + threadIdx.x;
-            if (idx < L * C) Sm[idx] = v[u];
+            if (idx < nb * L2) {
+                const int f = idx / L2, k = idx - f * L2;
+                Sm[(k >> 1) * C + 2 * f + (k & 1)] = v[u];  // degree d = k/2, column 2f + re/im
+            }
         }
     }
     for (int k = threadIdx.x; k < L + 16; k += blockDim.x)
@@ -432,7 +441,7 @@ constexpr size_t kLdsBytes = 96 * 1024;  // LDS per workgroup used by the Legend
 // LDS of the forward kernel besides E and O: generated tile, state, coefficients.
 size_t forward_fixed_lds(int H) {
     return sizeof(double) * kLatBlock * kPD + (sizeof(double2) + sizeof(double)) * (size_t)H +
-           sizeof(double2) * (kRun + 1);
+           sizeof(double2) * (kFwdRun + 1);
 }
 // Largest column chunk (even, <= 32) whose LDS fits kLdsBytes.
 int forward_chunk(int H, int C) {
@@ -481,7 +490,8 @@ int sh_setup(rexi_plan* pl) {
     std::vector<LegWork> ti;
     const int nl = (H + 15) / 16;
     for (int m = 0; m <= T; ++m) {
-        for (int r = 0; m + kRun * r <= T; ++r) tf.push_back(LegRun{m, m + kRun * r, run_base[m] + r, 0});
+        for (int r = 0; m + kFwdRun * r <= T; ++r)
+            tf.push_back(LegRun{m, m + kFwdRun * r, run_base[m] + r * (kFwdRun / kRun), 0});
     }
     // one order per workgroup: pairing m with T - m evens the work per wave
     // but halves the waves in flight, which measured slower (30 vs 26 us at T256)
