@@ -15,6 +15,10 @@ so only m >= 0 is stored and synthesis returns
   sum_n Re(xi_n^0) P_n^0 + 2 Re sum_{m>0} sum_n xi_n^m P_n^m e^{i m lam}.
 Grid layout: [B][nlat][nlon], latitude j = 0 northernmost (mu descending),
 lam_k = 2 pi k / nlon.
+
+Vector transforms (Eq. (1), Section 3): winds (u, v) from vorticity and
+divergence through the stream function and velocity potential, and back, with
+the latitude derivative of P_n^m taken from the differentiated recurrence.
 """
 from __future__ import annotations
 
@@ -65,7 +69,7 @@ def _eps(n, m):
     return math.sqrt((n * n - m * m) / (4.0 * n * n - 1.0))
 
 
-def legendre(T: int, mu: np.ndarray):
+def legendre(T: int, mu: np.ndarray, with_h: bool = False):
     """Orthonormal P_n^m(mu_j) for 0 <= m <= T, n = m..T.
 
     Returns a list P with P[m] of shape (T+1-m, len(mu)).  Three-term
@@ -76,11 +80,16 @@ def legendre(T: int, mu: np.ndarray):
     that columns whose seed underflows (large m near the poles) are still
     carried exactly through the recurrence; values below 1e-300 are returned
     as zero.
+
+    with_h: also return H[m], H_n^m = (1 - mu^2) dP_n^m/dmu, obtained by
+    differentiating the same recurrence (times 1 - mu^2):
+      eps_n H_n = (1 - mu^2) P_{n-1} + mu H_{n-1} - eps_{n-1} H_{n-2},
+    seeded with H_m^m = -m mu P_m^m.  Returns (P, H) then.
     """
     mu = np.asarray(mu, dtype=np.float64)
     s2 = np.maximum(1.0 - mu * mu, 0.0)
     logsin = 0.5 * np.log(s2)
-    out = []
+    out, outh = [], []
     logc = -0.5 * math.log(2.0)
     for m in range(T + 1):
         if m > 0:
@@ -89,30 +98,43 @@ def legendre(T: int, mu: np.ndarray):
         # Offset: carry values scaled by 2^-e so the seed is O(1).
         e = np.floor(logseed / math.log(2.0))
         scaled = np.exp(logseed - e * math.log(2.0))
-        col = np.zeros((T + 1 - m, len(mu)))
         p_prev2 = np.zeros_like(mu)
         p_prev = scaled
+        g_prev2 = np.zeros_like(mu)
+        g_prev = -m * mu * scaled
         vals = [p_prev]
+        hvals = [g_prev]
         for n in range(m + 1, T + 1):
             em = _eps(n - 1, m) if n - 1 > m else 0.0
-            pn = (mu * p_prev - em * p_prev2) / _eps(n, m)
-            # Renormalise the running pair when it grows large, moving the
+            en = _eps(n, m)
+            pn = (mu * p_prev - em * p_prev2) / en
+            gn = (s2 * p_prev + mu * g_prev - em * g_prev2) / en
+            # Renormalise the running values when they grow large, moving the
             # factor into the exponent (keeps the recurrence in range).
-            big = np.abs(pn) > 1e200
+            big = np.maximum(np.abs(pn), np.abs(gn)) > 1e200
             if np.any(big):
                 f = np.where(big, 2.0 ** -600, 1.0)
-                pn = pn * f
-                p_prev = p_prev * f
+                pn, p_prev, gn, g_prev = pn * f, p_prev * f, gn * f, g_prev * f
                 vals = [v * f for v in vals]
+                hvals = [v * f for v in hvals]
                 e = e + np.where(big, 600.0, 0.0)
             p_prev2, p_prev = p_prev, pn
+            g_prev2, g_prev = g_prev, gn
             vals.append(pn)
-        for i, v in enumerate(vals):
-            with np.errstate(over="ignore", under="ignore"):
-                col[i] = np.where(e > -1000, np.ldexp(v, np.clip(e, -2000, 2000).astype(np.int64)), 0.0)
-        col[np.abs(col) < 1e-300] = 0.0
-        out.append(col)
-    return out
+            hvals.append(gn)
+
+        def unscale(vs):
+            col = np.zeros((T + 1 - m, len(mu)))
+            for i, v in enumerate(vs):
+                with np.errstate(over="ignore", under="ignore"):
+                    col[i] = np.where(e > -1000, np.ldexp(v, np.clip(e, -2000, 2000).astype(np.int64)), 0.0)
+            col[np.abs(col) < 1e-300] = 0.0
+            return col
+
+        out.append(unscale(vals))
+        if with_h:
+            outh.append(unscale(hvals))
+    return (out, outh) if with_h else out
 
 
 def analysis(grid: np.ndarray, T: int) -> np.ndarray:
@@ -148,4 +170,78 @@ def synthesis(spec: np.ndarray, T: int, nlat: int, nlon: int) -> np.ndarray:
         else:
             ph = np.exp(1j * 2.0 * math.pi * mm * k / nlon)
             out += 2.0 * np.real(Fm[:, :, None] * ph[None, None, :])
+    return out
+
+
+def vortdiv_to_uv(vd: np.ndarray, T: int, nlat: int, nlon: int, radius: float) -> np.ndarray:
+    """Winds from vorticity and divergence (Eq. (1), Section 3).
+
+    vd: spectral [B][2][nspec] (zeta, delta).  Returns the grid [B][2][nlat][nlon]
+    of (u, v) in the units of radius * zeta.  With V = k x grad(psi) + grad(chi),
+    lap psi = zeta, lap chi = delta (lap -> -n(n+1)/a^2 on degree n; the n = 0
+    part carries no wind), and the cos(lat)-scaled winds U = u cos(lat),
+    V = v cos(lat) of Section 3:
+      U = -(1/a) (1 - mu^2) dpsi/dmu + (1/a) dchi/dlam,
+      V =  (1/a) dpsi/dlam + (1/a) (1 - mu^2) dchi/dmu,
+    summed directly over the modes with H_n^m = (1 - mu^2) dP_n^m/dmu from the
+    differentiated recurrence, then u = U / cos(lat), v = V / cos(lat).
+    """
+    vd = np.asarray(vd, dtype=np.complex128)
+    B = vd.shape[0]
+    mu, _ = gauss_latitudes(nlat)
+    P, Hm = legendre(T, mu, with_h=True)
+    k = np.arange(nlon)
+    U = np.zeros((B, nlat, nlon))
+    V = np.zeros((B, nlat, nlon))
+    for mm in range(T + 1):
+        o = index(T, mm, mm)
+        n = np.arange(mm, T + 1)
+        inv_lap = np.zeros(len(n))
+        inv_lap[n > 0] = -radius * radius / (n[n > 0] * (n[n > 0] + 1.0))
+        psi = vd[:, 0, o:o + T + 1 - mm] * inv_lap
+        chi = vd[:, 1, o:o + T + 1 - mm] * inv_lap
+        Um = (-np.einsum("bn,nj->bj", psi, Hm[mm]) + 1j * mm * np.einsum("bn,nj->bj", chi, P[mm])) / radius
+        Vm = (1j * mm * np.einsum("bn,nj->bj", psi, P[mm]) + np.einsum("bn,nj->bj", chi, Hm[mm])) / radius
+        if mm == 0:
+            U += Um.real[:, :, None]
+            V += Vm.real[:, :, None]
+        else:
+            ph = np.exp(1j * 2.0 * math.pi * mm * k / nlon)
+            U += 2.0 * np.real(Um[:, :, None] * ph[None, None, :])
+            V += 2.0 * np.real(Vm[:, :, None] * ph[None, None, :])
+    cosl = np.sqrt(1.0 - mu * mu)[None, :, None]
+    return np.stack([U / cosl, V / cosl], axis=1)
+
+
+def uv_to_vortdiv(uv: np.ndarray, T: int, radius: float) -> np.ndarray:
+    """Vorticity and divergence of the winds (Eq. (1), Section 3).
+
+    uv: grid [B][2][nlat][nlon] of (u, v).  Returns spectral [B][2][nspec] of
+    zeta = k . curl V and delta = div V:
+      zeta = (1/(a (1 - mu^2))) dV/dlam - (1/a) dU/dmu,
+      delta = (1/(a (1 - mu^2))) dU/dlam + (1/a) dV/dmu   (U, V = u, v times cos(lat)).
+    The analysis integral of the mu-derivative is taken by parts (U and V
+    vanish at the poles), so with u~ = u / cos(lat), v~ = v / cos(lat) and
+    their longitude coefficients u~_m, v~_m:
+      zeta_n^m = (1/a) sum_j w_j (i m v~_m P_n^m + u~_m H_n^m)(mu_j),
+      delta_n^m = (1/a) sum_j w_j (i m u~_m P_n^m - v~_m H_n^m)(mu_j).
+    """
+    uv = np.asarray(uv, dtype=np.float64)
+    B, _, nlat, nlon = uv.shape
+    mu, w = gauss_latitudes(nlat)
+    P, Hm = legendre(T, mu, with_h=True)
+    cosl = np.sqrt(1.0 - mu * mu)[None, :, None]
+    k = np.arange(nlon)
+    m = np.arange(T + 1)
+    E = np.exp(-1j * 2.0 * math.pi * np.outer(m, k) / nlon) / nlon
+    Fu = np.einsum("bjk,mk->bjm", uv[:, 0] / cosl, E)
+    Fv = np.einsum("bjk,mk->bjm", uv[:, 1] / cosl, E)
+    out = np.zeros((B, 2, nspec(T)), dtype=np.complex128)
+    for mm in range(T + 1):
+        o = index(T, mm, mm)
+        sl = slice(o, o + T + 1 - mm)
+        out[:, 0, sl] = (1j * mm * np.einsum("nj,j,bj->bn", P[mm], w, Fv[:, :, mm])
+                         + np.einsum("nj,j,bj->bn", Hm[mm], w, Fu[:, :, mm])) / radius
+        out[:, 1, sl] = (1j * mm * np.einsum("nj,j,bj->bn", P[mm], w, Fu[:, :, mm])
+                         - np.einsum("nj,j,bj->bn", Hm[mm], w, Fv[:, :, mm])) / radius
     return out
