@@ -176,6 +176,33 @@ def bump_runs(rexi, synth, torch, dev, reps=3):
     return out
 
 
+def vector_run(plan, u, T, nlat, torch, reps=25):
+    """Vector transforms of the benchmark states (winds from vorticity and
+    divergence and back, Eq. (1)), median event time per call over `reps`
+    calls.  Both run the Legendre contraction at degree T + 1 on 2 S fields."""
+    S = u.shape[0]
+    uv = plan.vortdiv_to_uv(u)
+    back = torch.empty_like(u)
+    plan.uv_to_vortdiv(uv, out=back)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("vortdiv_to_uv_ms", lambda: plan.vortdiv_to_uv(u, out=uv)),
+                     ("uv_to_vortdiv_ms", lambda: plan.uv_to_vortdiv(uv, out=back))):
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        out[name] = sorted(times)[len(times) // 2]
+    out["pairs"] = S
+    out["legendre_flops_per_call"] = legendre_flops(T + 1, nlat, 2 * S)
+    out["note"] = "each call: one spectral recombination, FFTs and the Legendre contraction at degree T + 1"
+    return out
+
+
 def dispersion_run(rexi, synth, torch, dev):
     """Numerical dispersion of the step on the f-sphere (Section 6.3): every
     mode stepped once on the GPU, log-eigenvalues against the exact frequencies."""
@@ -339,6 +366,7 @@ def main():
         rec["bumps"] = bump_runs(rexi, synth, torch, dev)
         rec["dispersion"] = dispersion_run(rexi, synth, torch, dev)
     rec["graph_replay_median"] = graph_replay_medians(plan, u)
+    rec["vector_transforms"] = vector_run(plan, u, T, w.nlat, torch)
     if not args.no_cpu_baseline:
         us = torch.from_numpy(synth.random_state(T, S, 0)).to(dev)
         gf = plan.step(us).cpu().numpy()

@@ -149,6 +149,33 @@ int sh_forward(rexi_plan *plan, const double *grid, void *spec, int B, void *str
  *   spec  device complex128 [B][nspec];  grid  device float64 [B][nlat][nlon] */
 int sh_inverse(rexi_plan *plan, const void *spec, double *grid, int B, void *stream);
 
+/* Winds from vorticity and divergence (Eq. (1): V = k x grad(psi) + grad(chi)
+ * with lap psi = zeta, lap chi = delta; Section 3's scaled winds
+ * U = u cos(lat), V = v cos(lat)).  The latitude derivative raises the degree
+ * by one, so U and V are synthesised at degree T + 1 (orders m <= T) and
+ * divided by cos(lat) on the grid; the n = 0 coefficients carry no wind.
+ *   vd      device complex128; pair b: zeta [nspec] at vd + b * stride, delta
+ *           [nspec] right after it (stride in complex entries, >= 2 nspec;
+ *           stride 3 nspec with vd = u + nspec reads the (zeta, delta) of the
+ *           states [S][3][nspec] of rexi_step)
+ *   uv      device float64 [B][2][nlat][nlon]: u (eastward), v (northward), in
+ *           the units of radius * zeta
+ *   1 <= 2 B <= max_fields (REXI_EUNSUPPORTED above).  Exact (to rounding)
+ *   inverse of sh_uv_to_vortdiv on such winds when nlat >= T + 1 and
+ *   nlon > 2 T.  Needs a plan with a grid; no allocation. */
+int sh_vortdiv_to_uv(rexi_plan *plan, const void *vd, long long stride, double *uv, int B, void *stream);
+
+/* Vorticity and divergence of winds (Eq. (1)): zeta = k . curl V,
+ * delta = div V, analysed on the Gaussian grid (Section 3).  The integral of
+ * the latitude derivative is taken by parts, so the quadrature acts on
+ * u / cos(lat) and v / cos(lat) at degree T + 1 (no pole values are needed).
+ *   uv      device float64 [B][2][nlat][nlon] (u, v)
+ *   vd      device complex128, layout as for sh_vortdiv_to_uv; only the zeta
+ *           and delta entries of each pair are written (a state's Phi between
+ *           them is left as it is)
+ *   1 <= 2 B <= max_fields; output and input must not overlap. */
+int sh_uv_to_vortdiv(rexi_plan *plan, const double *uv, void *vd, long long stride, int B, void *stream);
+
 /* nsteps T-REXI steps (Section 4.2, Algorithm 1's sum and reduction) of S
  * states: u1 = R^nsteps u0 with
  *   R = sum_k beta+_k (alpha_k + dt L)^{-1} + sum_k beta-_k (alpha_k - dt L)^{-1}.

@@ -46,6 +46,17 @@ void gauss_legendre(int nlat, std::vector<double>& mu, std::vector<double>& w);
 std::vector<double> legendre_coefs(int T);
 std::vector<double> legendre_restarts(int T, int run, const std::vector<double>& mu, std::vector<int>& run_base);
 
+// Device tables of the Legendre kernels for degrees 0..T (orders m <= the
+// plan's truncation): restart rows, recurrence coefficients and work lists.
+struct LegTables {
+    int T = 0;
+    double* d_restart = nullptr;  // [row][2][nhalf]
+    double* d_lcoef = nullptr;    // [nspec(T)][2]
+    void* d_tiles_f = nullptr;    // forward runs
+    void* d_tiles_i = nullptr;    // inverse work
+    int ntiles_f = 0, ntiles_i = 0;
+};
+
 __host__ __device__ inline long long spec_offset(int T, int m) {
     return (long long)m * (T + 1) - (long long)m * (m - 1) / 2;
 }
@@ -141,15 +152,14 @@ struct rexi_plan {
     // transforms
     int nlat = 0, nlon = 0, nhalf = 0;
     std::vector<double> mu, w;
-    double* d_restart = nullptr;  // Legendre restart rows [row][2][nhalf]
-    double* d_lcoef = nullptr;    // Legendre recurrence coefficients [nspec][2]
+    rexi::LegTables leg;          // degrees 0..T (scalar transforms)
+    rexi::LegTables legv;         // degrees 0..T+1 (vector transforms)
     double* d_mu = nullptr;       // northern Gauss nodes [nhalf]
     double* d_wts = nullptr;      // Gauss weights
+    double* d_rcos = nullptr;     // 1 / cos(lat_j) [nlat]
     double* d_four = nullptr;     // Fourier coefficients workspace [T+1][nlat][2B]
     double2* d_twiddle = nullptr; // FFT twiddles
-    void* d_tiles_f = nullptr;    // Legendre tiles, forward / inverse
-    void* d_tiles_i = nullptr;
-    int ntiles_f = 0, ntiles_i = 0;
+    double2* d_vspec = nullptr;   // vector transforms: [max_fields][nspec(T+1)]
 
     // f-sphere variant: constant Coriolis parameter times dt, poles
     // [N][3] (alpha, beta+, beta-), one state-sized work buffer

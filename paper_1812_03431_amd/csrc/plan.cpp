@@ -30,6 +30,7 @@ hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int b
 int sh_setup(rexi_plan* pl);
 void sh_release(rexi_plan* pl);
 int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStream_t s);
+int sh_vec_run(rexi_plan* pl, const void* in, void* out, long long stride, int B, bool to_uv, hipStream_t s);
 
 namespace {
 thread_local std::string g_err;
@@ -849,6 +850,16 @@ int sh_forward(rexi_plan* plan, const double* grid, void* spec, int B, void* str
 int sh_inverse(rexi_plan* plan, const void* spec, double* grid, int B, void* stream) {
     if (!plan) return fail(REXI_EINVAL, "plan is NULL");
     return sh_run(plan, spec, grid, B, false, (hipStream_t)stream);
+}
+
+int sh_vortdiv_to_uv(rexi_plan* plan, const void* vd, long long stride, double* uv, int B, void* stream) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    return sh_vec_run(plan, vd, uv, stride, B, true, (hipStream_t)stream);
+}
+
+int sh_uv_to_vortdiv(rexi_plan* plan, const double* uv, void* vd, long long stride, int B, void* stream) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    return sh_vec_run(plan, uv, vd, stride, B, false, (hipStream_t)stream);
 }
 
 }  // extern "C"

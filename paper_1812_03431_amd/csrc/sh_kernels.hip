@@ -49,10 +49,11 @@ __device__ void fft_lds(double2* X, const double2* tw, int n, bool inverse) {
     }
 }
 
-// grid [B][nlat][nlon] -> Fw[m][j][c] for m <= T.
+// grid [B][nlat][nlon] -> Fw[m][j][c] for m <= T; row j scaled by rs[j]
+// (rs may be NULL: no scaling).
 __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ grid, double* __restrict__ Fw,
-                                                     const double2* __restrict__ tw, int nlat, int nlon, int bits,
-                                                     int T, int C) {
+                                                     const double2* __restrict__ tw, const double* __restrict__ rs,
+                                                     int nlat, int nlon, int bits, int T, int C) {
     extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
     double2* tws = X + nlon;
     const int row = blockIdx.x;  // b * nlat + j
@@ -78,7 +79,7 @@ __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ 
     }
     __syncthreads();
     fft_lds(X, tws, nlon, false);
-    const double inv = 1.0 / nlon;
+    const double inv = (rs ? rs[j] : 1.0) / nlon;
     for (int m = threadIdx.x; m <= T; m += blockDim.x) {
         const double2 v = X[m];
         double* dst = Fw + ((long long)m * nlat + j) * C + 2 * b;
@@ -87,10 +88,10 @@ __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ 
     }
 }
 
-// Fw[m][j][c] -> grid [B][nlat][nlon]
+// Fw[m][j][c] -> grid [B][nlat][nlon]; row j scaled by rs[j] (rs may be NULL)
 __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ Fw, double* __restrict__ grid,
-                                                     const double2* __restrict__ tw, int nlat, int nlon, int bits,
-                                                     int T, int C) {
+                                                     const double2* __restrict__ tw, const double* __restrict__ rs,
+                                                     int nlat, int nlon, int bits, int T, int C) {
     extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
     double2* tws = X + nlon;
     const int row = blockIdx.x;
@@ -123,7 +124,8 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
     __syncthreads();
     fft_lds(X, tws, nlon, true);
     double* dst = grid + (long long)row * nlon;
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) dst[k] = X[k].x;
+    const double sc = rs ? rs[j] : 1.0;
+    for (int k = threadIdx.x; k < nlon; k += blockDim.x) dst[k] = X[k].x * sc;
 }
 
 // Legendre contractions with P_n^m generated on the device.  The table
@@ -436,6 +438,81 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     if (wk.m2 >= 0) inverse_order<NCT>(o1, restart, Fw, T, nlat, H, Cs, c_off, C, t, lane, x, jok);
 }
 
+// Vector transforms (Eq. (1): V = k x grad(psi) + grad(chi), lap psi = zeta,
+// lap chi = delta; Section 3's scaled winds U = u cos(lat), V = v cos(lat)).
+// On degree n, lap = -n(n+1)/a^2, and with eps_n = sqrt((n^2 - m^2)/(4n^2 - 1))
+// the latitude derivative of the orthonormal P_n^m obeys
+//   (1 - mu^2) dP_n^m/dmu = (n + 1) eps_n P_{n-1}^m - n eps_{n+1} P_{n+1}^m,
+// so the derivative moves a coefficient one degree up or down and U, V are
+// fields of degree T + 1.  Written through zeta and delta directly:
+//   U_n = -a [ eps_n zeta_{n-1} / n - eps_{n+1} zeta_{n+1} / (n+1) + i m delta_n / (n(n+1)) ]
+//   V_n = -a [ i m zeta_n / (n(n+1)) - eps_n delta_{n-1} / n + eps_{n+1} delta_{n+1} / (n+1) ]
+// over m <= n <= T + 1, terms outside m <= degree <= T dropped (the n = 0
+// coefficient carries no wind).  Back: with A, B the analyses (degree T + 1)
+// of u / cos(lat), v / cos(lat), integration by parts in mu gives
+//   zeta_n  = (1/a) [ i m B_n - n eps_{n+1} A_{n+1} + (n+1) eps_n A_{n-1} ]
+//   delta_n = (1/a) [ i m A_n + n eps_{n+1} B_{n+1} - (n+1) eps_n B_{n-1} ].
+// Layouts: vd pair b at vd + b * stride (zeta, then delta at + nspec(T));
+// uvs / ab fields 2b (U or A) and 2b + 1 (V or B) of nspec(T + 1) each.
+__device__ __forceinline__ double eps_nm(int n, int m) {
+    return sqrt((double)(n * n - m * m) / (4.0 * n * n - 1.0));
+}
+
+__global__ void __launch_bounds__(256) k_vd_to_uv_spec(const double2* __restrict__ vd, long long stride,
+                                                      double2* __restrict__ uvs, int T, double a) {
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int n = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > T + 1) return;
+    const double2* z = vd + b * stride + spec_offset(T, m) - m;  // z[k] = zeta_k^m, m <= k <= T
+    const double2* d = z + nspec_of(T);
+    double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
+    if (n - 1 >= max(m, 1)) {
+        const double e = eps_nm(n, m) / n;
+        const double2 zl = z[n - 1], dl = d[n - 1];
+        ur += e * zl.x, ui += e * zl.y;
+        vr -= e * dl.x, vi -= e * dl.y;
+    }
+    if (n + 1 <= T) {
+        const double e = eps_nm(n + 1, m) / (n + 1);
+        const double2 zh = z[n + 1], dh = d[n + 1];
+        ur -= e * zh.x, ui -= e * zh.y;
+        vr += e * dh.x, vi += e * dh.y;
+    }
+    if (m > 0 && n <= T) {
+        const double f = (double)m / ((double)n * (n + 1));
+        const double2 zc = z[n], dc = d[n];
+        ur -= f * dc.y, ui += f * dc.x;
+        vr -= f * zc.y, vi += f * zc.x;
+    }
+    const long long ns1 = nspec_of(T + 1), o = spec_offset(T + 1, m) + (n - m);
+    uvs[(2LL * b) * ns1 + o] = make_double2(-a * ur, -a * ui);
+    uvs[(2LL * b + 1) * ns1 + o] = make_double2(-a * vr, -a * vi);
+}
+
+__global__ void __launch_bounds__(256) k_uv_spec_to_vd(const double2* __restrict__ ab, double2* __restrict__ vd,
+                                                      long long stride, int T, double a) {
+    const int m = blockIdx.y, b = blockIdx.z;
+    const int n = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > T) return;
+    const long long ns1 = nspec_of(T + 1);
+    const double2* A = ab + (2LL * b) * ns1 + spec_offset(T + 1, m) - m;  // A[k], m <= k <= T + 1
+    const double2* Bv = A + ns1;
+    const double2 ac = A[n], bc = Bv[n], ah = A[n + 1], bh = Bv[n + 1];
+    const double eh = n * eps_nm(n + 1, m);
+    double zr = -m * bc.y - eh * ah.x, zi = m * bc.x - eh * ah.y;
+    double dr = -m * ac.y + eh * bh.x, di = m * ac.x + eh * bh.y;
+    if (n - 1 >= m) {
+        const double el = (n + 1) * eps_nm(n, m);
+        const double2 al = A[n - 1], bl = Bv[n - 1];
+        zr += el * al.x, zi += el * al.y;
+        dr -= el * bl.x, di -= el * bl.y;
+    }
+    const double ia = 1.0 / a;
+    double2* z = vd + b * stride + spec_offset(T, m) + (n - m);
+    z[0] = make_double2(zr * ia, zi * ia);
+    z[nspec_of(T)] = make_double2(dr * ia, di * ia);
+}
+
 constexpr size_t kLdsBytes = 96 * 1024;  // LDS per workgroup used by the Legendre kernels
 
 // LDS of the forward kernel besides E and O: generated tile, state, coefficients.
@@ -463,6 +540,116 @@ int inverse_chunk(int T, int C) {
 
 }  // namespace
 
+namespace {
+
+int device_alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) return fail(REXI_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    return REXI_OK;
+}
+
+// Restart rows, coefficients and work lists of the Legendre kernels for
+// degrees 0..Tt over orders m <= the plan's T.
+int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& north) {
+    const int T = pl->T, H = pl->nhalf;
+    std::vector<int> run_base;
+    std::vector<double> restart = legendre_restarts(Tt, kRun, north, run_base);
+    std::vector<double> lcoef = legendre_coefs(Tt);
+    // forward: one workgroup per run, longest orders first (they come first);
+    // inverse: four latitude tiles (one per wave) of one order.  One order
+    // per workgroup: pairing m with T - m evens the work per wave but halves
+    // the waves in flight, which measured slower (30 vs 26 us at T256)
+    std::vector<LegRun> tf;
+    std::vector<LegWork> ti;
+    const int nl = (H + 15) / 16;
+    for (int m = 0; m <= T; ++m)
+        for (int r = 0; m + kFwdRun * r <= Tt; ++r)
+            tf.push_back(LegRun{m, m + kFwdRun * r, run_base[m] + r * (kFwdRun / kRun), 0});
+    for (int m = 0; m <= T; ++m)
+        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m], -1, 0});
+    t.T = Tt;
+    int rc = device_alloc((void**)&t.d_restart, restart.size() * sizeof(double));
+    if (!rc) rc = device_alloc((void**)&t.d_lcoef, lcoef.size() * sizeof(double));
+    if (!rc) rc = device_alloc((void**)&t.d_tiles_f, tf.size() * sizeof(LegRun));
+    if (!rc) rc = device_alloc((void**)&t.d_tiles_i, ti.size() * sizeof(LegWork));
+    if (rc) return rc;
+    REXI_HIP(hipMemcpy(t.d_restart, restart.data(), restart.size() * sizeof(double), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(t.d_lcoef, lcoef.data(), lcoef.size() * sizeof(double), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(t.d_tiles_f, tf.data(), tf.size() * sizeof(LegRun), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(t.d_tiles_i, ti.data(), ti.size() * sizeof(LegWork), hipMemcpyHostToDevice));
+    t.ntiles_f = (int)tf.size();
+    t.ntiles_i = (int)ti.size();
+    return REXI_OK;
+}
+
+void leg_release(LegTables& t) {
+    void* ptrs[] = {t.d_restart, t.d_lcoef, t.d_tiles_f, t.d_tiles_i};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    t = LegTables{};
+}
+
+int fft_bits(int nlon) {
+    int bits = 0;
+    while ((1 << bits) < nlon) ++bits;
+    return bits;
+}
+
+// grid rows [nf][nlat][nlon] -> Fw (C = 2 nf columns), row scale rs or NULL
+int fft_forward(rexi_plan* pl, const double* grid, int nf, const double* rs, hipStream_t s) {
+    const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_forward, dim3(nf * pl->nlat), dim3(256), lds, s, grid, pl->d_four, pl->d_twiddle, rs,
+                       pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
+    REXI_HIP(hipGetLastError());
+    return REXI_OK;
+}
+
+int fft_inverse(rexi_plan* pl, double* grid, int nf, const double* rs, hipStream_t s) {
+    const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_inverse, dim3(nf * pl->nlat), dim3(256), lds, s, pl->d_four, grid, pl->d_twiddle, rs,
+                       pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
+    REXI_HIP(hipGetLastError());
+    return REXI_OK;
+}
+
+// Fw (C columns) -> spec [C/2][nspec(t.T)]
+int leg_forward(rexi_plan* pl, const LegTables& t, double* spec, int C, hipStream_t s) {
+    const int H = pl->nhalf;
+    const double2* coef = reinterpret_cast<const double2*>(t.d_lcoef);
+    const int cc = forward_chunk(H, C);
+    for (int c0 = 0; c0 < C; c0 += cc) {
+        const int w = std::min(cc, C - c0);
+        const size_t lf = sizeof(double) * 2 * (size_t)H * w + forward_fixed_lds(H);
+        hipLaunchKernelGGL(k_legendre_forward, dim3(t.ntiles_f), dim3(256), lf, s, (const LegRun*)t.d_tiles_f,
+                           t.d_restart, coef, pl->d_mu, pl->d_wts, pl->d_four, spec, t.T, pl->nlat, H, C, c0, w);
+        REXI_HIP(hipGetLastError());
+    }
+    return REXI_OK;
+}
+
+// spec [C/2][nspec(t.T)] -> Fw (C columns)
+int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hipStream_t s) {
+    const int H = pl->nhalf;
+    const double2* coef = reinterpret_cast<const double2*>(t.d_lcoef);
+    const int cc = inverse_chunk(t.T, C);
+    for (int c0 = 0; c0 < C; c0 += cc) {
+        const int w = std::min(cc, C - c0);
+        const size_t li = inverse_lds(t.T, w);
+        if (w > 16)
+            hipLaunchKernelGGL(k_legendre_inverse<2>, dim3(t.ntiles_i), dim3(256), li, s,
+                               (const LegWork*)t.d_tiles_i, t.d_restart, coef, pl->d_mu, spec, pl->d_four, t.T,
+                               pl->nlat, H, C, c0, w);
+        else
+            hipLaunchKernelGGL(k_legendre_inverse<1>, dim3(t.ntiles_i), dim3(256), li, s,
+                               (const LegWork*)t.d_tiles_i, t.d_restart, coef, pl->d_mu, spec, pl->d_four, t.T,
+                               pl->nlat, H, C, c0, w);
+        REXI_HIP(hipGetLastError());
+    }
+    return REXI_OK;
+}
+
+}  // namespace
+
 int sh_setup(rexi_plan* pl) {
     const int T = pl->T, nlat = pl->prm.nlat, nlon = pl->prm.nlon;
     if (nlat % 2) return fail(REXI_EUNSUPPORTED, "nlat must be even");
@@ -474,52 +661,32 @@ int sh_setup(rexi_plan* pl) {
     const int H = pl->nhalf;
     gauss_legendre(nlat, pl->mu, pl->w);
     std::vector<double> north(pl->mu.begin(), pl->mu.begin() + H);
-    std::vector<int> run_base;
-    std::vector<double> restart = legendre_restarts(T, kRun, north, run_base);
-    std::vector<double> lcoef = legendre_coefs(T);
     std::vector<double> wn(pl->w.begin(), pl->w.begin() + H);
+    std::vector<double> rcos(nlat);
+    for (int j = 0; j < nlat; ++j) {
+        const long double x = pl->mu[j];
+        rcos[j] = (double)(1.0L / sqrtl((1.0L - x) * (1.0L + x)));
+    }
     std::vector<double2> tw(nlon / 2);
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int k = 0; k < nlon / 2; ++k) {
         const long double a = -2 * pi * k / nlon;
         tw[k] = make_double2((double)cosl(a), (double)sinl(a));
     }
-    // forward: one workgroup per run, longest orders first (they come first);
-    // inverse: four latitude tiles (one per wave) of one order
-    std::vector<LegRun> tf;
-    std::vector<LegWork> ti;
-    const int nl = (H + 15) / 16;
-    for (int m = 0; m <= T; ++m) {
-        for (int r = 0; m + kFwdRun * r <= T; ++r)
-            tf.push_back(LegRun{m, m + kFwdRun * r, run_base[m] + r * (kFwdRun / kRun), 0});
-    }
-    // one order per workgroup: pairing m with T - m evens the work per wave
-    // but halves the waves in flight, which measured slower (30 vs 26 us at T256)
-    for (int m = 0; m <= T; ++m)
-        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m], -1, 0});
-    auto alloc = [&](void** p, size_t bytes) -> int {
-        hipError_t e = hipMalloc(p, bytes ? bytes : 1);
-        if (e != hipSuccess) return fail(REXI_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
-        return REXI_OK;
-    };
-    int rc = alloc((void**)&pl->d_restart, restart.size() * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_lcoef, lcoef.size() * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_mu, north.size() * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_wts, wn.size() * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_twiddle, tw.size() * sizeof(double2));
-    if (!rc) rc = alloc((void**)&pl->d_four, (size_t)(T + 1) * nlat * 2 * pl->prm.max_fields * sizeof(double));
-    if (!rc) rc = alloc((void**)&pl->d_tiles_f, tf.size() * sizeof(LegRun));
-    if (!rc) rc = alloc((void**)&pl->d_tiles_i, ti.size() * sizeof(LegWork));
+    int rc = leg_build(pl, pl->leg, T, north);
+    if (!rc) rc = leg_build(pl, pl->legv, T + 1, north);
+    if (!rc) rc = device_alloc((void**)&pl->d_mu, north.size() * sizeof(double));
+    if (!rc) rc = device_alloc((void**)&pl->d_wts, wn.size() * sizeof(double));
+    if (!rc) rc = device_alloc((void**)&pl->d_rcos, rcos.size() * sizeof(double));
+    if (!rc) rc = device_alloc((void**)&pl->d_twiddle, tw.size() * sizeof(double2));
+    if (!rc) rc = device_alloc((void**)&pl->d_four, (size_t)(T + 1) * nlat * 2 * pl->prm.max_fields * sizeof(double));
+    if (!rc && pl->prm.max_fields >= 2)
+        rc = device_alloc((void**)&pl->d_vspec, (size_t)pl->prm.max_fields * nspec_of(T + 1) * sizeof(double2));
     if (rc) return rc;
-    REXI_HIP(hipMemcpy(pl->d_restart, restart.data(), restart.size() * sizeof(double), hipMemcpyHostToDevice));
-    REXI_HIP(hipMemcpy(pl->d_lcoef, lcoef.data(), lcoef.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_mu, north.data(), north.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_wts, wn.data(), wn.size() * sizeof(double), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(pl->d_rcos, rcos.data(), rcos.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
-    REXI_HIP(hipMemcpy(pl->d_tiles_f, tf.data(), tf.size() * sizeof(LegRun), hipMemcpyHostToDevice));
-    REXI_HIP(hipMemcpy(pl->d_tiles_i, ti.data(), ti.size() * sizeof(LegWork), hipMemcpyHostToDevice));
-    pl->ntiles_f = (int)tf.size();
-    pl->ntiles_i = (int)ti.size();
     // dynamic LDS above 64 KB per workgroup
     const int fft_lds = (nlon + nlon / 2) * (int)sizeof(double2);
     REXI_HIP(hipFuncSetAttribute((const void*)k_fft_forward, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
@@ -534,17 +701,23 @@ int sh_setup(rexi_plan* pl) {
 }
 
 void sh_release(rexi_plan* pl) {
-    void* ptrs[] = {pl->d_restart, pl->d_lcoef, pl->d_mu, pl->d_wts, pl->d_twiddle, pl->d_four, pl->d_tiles_f, pl->d_tiles_i};
+    leg_release(pl->leg);
+    leg_release(pl->legv);
+    void* ptrs[] = {pl->d_mu, pl->d_wts, pl->d_rcos, pl->d_twiddle, pl->d_four, pl->d_vspec};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    pl->d_restart = nullptr;
-    pl->d_lcoef = nullptr;
     pl->d_mu = nullptr;
     pl->d_wts = nullptr;
+    pl->d_rcos = nullptr;
     pl->d_twiddle = nullptr;
     pl->d_four = nullptr;
-    pl->d_tiles_f = nullptr;
-    pl->d_tiles_i = nullptr;
+    pl->d_vspec = nullptr;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
 }
 
 int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStream_t s) {
@@ -554,50 +727,53 @@ int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStr
     if (B > pl->prm.max_fields) return fail(REXI_EUNSUPPORTED, "B exceeds the plan's max_fields");
     const size_t gbytes = (size_t)B * pl->nlat * pl->nlon * sizeof(double);
     const size_t sbytes = (size_t)B * pl->nspec * 16;
-    const char* a = (const char*)in;
-    const char* o = (const char*)out;
-    const size_t na = forward ? gbytes : sbytes, no = forward ? sbytes : gbytes;
-    if (a < o + no && o < a + na) return fail(REXI_EALIAS, "output overlaps input");
+    if (overlaps(in, forward ? gbytes : sbytes, out, forward ? sbytes : gbytes))
+        return fail(REXI_EALIAS, "output overlaps input");
     const int C = 2 * B;
-    const int H = pl->nhalf;
-    int bits = 0;
-    while ((1 << bits) < pl->nlon) ++bits;
-    const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
-    const double2* coef = reinterpret_cast<const double2*>(pl->d_lcoef);
+    int rc;
     if (forward) {
-        hipLaunchKernelGGL(k_fft_forward, dim3(B * pl->nlat), dim3(256), lds, s, (const double*)in, pl->d_four,
-                           pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);
-        REXI_HIP(hipGetLastError());
+        if ((rc = fft_forward(pl, (const double*)in, B, nullptr, s))) return rc;
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_FWD, s));
-        const int cc = forward_chunk(H, C);
-        for (int c0 = 0; c0 < C; c0 += cc) {
-            const int w = std::min(cc, C - c0);
-            const size_t lf = sizeof(double) * 2 * (size_t)H * w + forward_fixed_lds(H);
-            hipLaunchKernelGGL(k_legendre_forward, dim3(pl->ntiles_f), dim3(256), lf, s,
-                               (const LegRun*)pl->d_tiles_f, pl->d_restart, coef, pl->d_mu, pl->d_wts, pl->d_four,
-                               (double*)out, pl->T, pl->nlat, H, C, c0, w);
-            REXI_HIP(hipGetLastError());
-        }
+        if ((rc = leg_forward(pl, pl->leg, (double*)out, C, s))) return rc;
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_FWD, s));
     } else {
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_INV, s));
-        const int cc = inverse_chunk(pl->T, C);
-        for (int c0 = 0; c0 < C; c0 += cc) {
-            const int w = std::min(cc, C - c0);
-            const size_t li = inverse_lds(pl->T, w);
-            if (w > 16)
-                hipLaunchKernelGGL(k_legendre_inverse<2>, dim3(pl->ntiles_i), dim3(256), li, s,
-                                   (const LegWork*)pl->d_tiles_i, pl->d_restart, coef, pl->d_mu, (const double*)in,
-                                   pl->d_four, pl->T, pl->nlat, H, C, c0, w);
-            else
-                hipLaunchKernelGGL(k_legendre_inverse<1>, dim3(pl->ntiles_i), dim3(256), li, s,
-                                   (const LegWork*)pl->d_tiles_i, pl->d_restart, coef, pl->d_mu, (const double*)in,
-                                   pl->d_four, pl->T, pl->nlat, H, C, c0, w);
-            REXI_HIP(hipGetLastError());
-        }
+        if ((rc = leg_inverse(pl, pl->leg, (const double*)in, C, s))) return rc;
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_INV, s));
-        hipLaunchKernelGGL(k_fft_inverse, dim3(B * pl->nlat), dim3(256), lds, s, pl->d_four, (double*)out,
-                           pl->d_twiddle, pl->nlat, pl->nlon, bits, pl->T, C);
+        if ((rc = fft_inverse(pl, (double*)out, B, nullptr, s))) return rc;
+    }
+    return REXI_OK;
+}
+
+// Vector transforms: vd pairs (zeta, delta) at stride `stride` complex entries
+// <-> winds uv [B][2][nlat][nlon].  Through the degree-(T+1) fields of
+// u / cos(lat), v / cos(lat) (forward) or u cos(lat), v cos(lat) (inverse) in
+// d_vspec; the 1 / cos(lat) row scale is applied inside the FFT kernels.
+int sh_vec_run(rexi_plan* pl, const void* in, void* out, long long stride, int B, bool to_uv, hipStream_t s) {
+    if (pl->nlat == 0) return fail(REXI_EUNSUPPORTED, "plan was created without a grid (nlat = nlon = 0)");
+    if (!in || !out) return fail(REXI_EINVAL, "NULL pointer");
+    if (B < 1) return fail(REXI_EINVAL, "B must be >= 1");
+    if (stride < 2 * pl->nspec) return fail(REXI_EINVAL, "stride must be at least 2 nspec");
+    if (2LL * B > pl->prm.max_fields) return fail(REXI_EUNSUPPORTED, "2 B exceeds the plan's max_fields");
+    const size_t gbytes = (size_t)2 * B * pl->nlat * pl->nlon * sizeof(double);
+    const size_t sbytes = ((size_t)(B - 1) * stride + 2 * (size_t)pl->nspec) * 16;
+    if (overlaps(in, to_uv ? sbytes : gbytes, out, to_uv ? gbytes : sbytes))
+        return fail(REXI_EALIAS, "output overlaps input");
+    const int T = pl->T;
+    const int C = 4 * B;
+    const dim3 grid((T + 2 + 255) / 256, T + 1, B);
+    int rc;
+    if (to_uv) {
+        hipLaunchKernelGGL(k_vd_to_uv_spec, grid, dim3(256), 0, s, (const double2*)in, stride, pl->d_vspec, T,
+                           pl->prm.radius);
+        REXI_HIP(hipGetLastError());
+        if ((rc = leg_inverse(pl, pl->legv, (const double*)pl->d_vspec, C, s))) return rc;
+        if ((rc = fft_inverse(pl, (double*)out, 2 * B, pl->d_rcos, s))) return rc;
+    } else {
+        if ((rc = fft_forward(pl, (const double*)in, 2 * B, pl->d_rcos, s))) return rc;
+        if ((rc = leg_forward(pl, pl->legv, (double*)pl->d_vspec, C, s))) return rc;
+        hipLaunchKernelGGL(k_uv_spec_to_vd, grid, dim3(256), 0, s, (const double2*)pl->d_vspec, (double2*)out,
+                           stride, T, pl->prm.radius);
         REXI_HIP(hipGetLastError());
     }
     return REXI_OK;

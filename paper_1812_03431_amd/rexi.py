@@ -48,6 +48,8 @@ def load_library():
         "rexi_plan_coeffs": [P, P, P, P],
         "sh_forward": [P, P, P, c_int, P],
         "sh_inverse": [P, P, P, c_int, P],
+        "sh_vortdiv_to_uv": [P, P, c_longlong, P, c_int, P],
+        "sh_uv_to_vortdiv": [P, P, P, c_longlong, c_int, P],
         "rexi_step": [P, P, P, c_int, c_int, P],
         "rexi_step_adjoint": [P, P, P, c_int, c_int, P],
         "rexi_step_per_term": [P, P, P, c_int, P],
@@ -193,6 +195,47 @@ class Plan:
         _need(out, torch.float64, (B, self.params.nlat, self.params.nlon), "grid")
         _check(self._lib.sh_inverse(self._h, c_void_p(spec.data_ptr()), c_void_p(out.data_ptr()), B,
                                     _stream_handle(stream)), "sh_inverse")
+        return out
+
+    def _vd_view(self, vd, name):
+        """(pointer to zeta of pair 0, stride in complex entries, B) of a
+        [B][2][nspec] (zeta, delta) tensor or a [S][3][nspec] state tensor."""
+        import torch
+        if vd.dim() != 3 or vd.shape[1] not in (2, 3):
+            raise ValueError(f"{name} must have shape (B, 2, nspec) or (S, 3, nspec), got {tuple(vd.shape)}")
+        B, k = vd.shape[0], vd.shape[1]
+        _need(vd, torch.complex128, (B, k, self.nspec), name)
+        off = (k - 2) * self.nspec * 16
+        return c_void_p(vd.data_ptr() + off), k * self.nspec, B
+
+    def vortdiv_to_uv(self, vd, out=None, stream=None):
+        """Winds (u, v) [B][2][nlat][nlon] from vorticity and divergence
+        (sh_vortdiv_to_uv).  vd: [B][2][nspec] (zeta, delta) or states
+        [S][3][nspec] (Phi, zeta, delta)."""
+        import torch
+        ptr, stride, B = self._vd_view(vd, "vd")
+        shape = (B, 2, self.params.nlat, self.params.nlon)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=vd.device)
+        _need(out, torch.float64, shape, "uv")
+        _check(self._lib.sh_vortdiv_to_uv(self._h, ptr, stride, c_void_p(out.data_ptr()), B,
+                                          _stream_handle(stream)), "sh_vortdiv_to_uv")
+        return out
+
+    def uv_to_vortdiv(self, uv, out=None, stream=None):
+        """Vorticity and divergence of winds uv [B][2][nlat][nlon]
+        (sh_uv_to_vortdiv).  out: [B][2][nspec], or states [B][3][nspec] whose
+        zeta and delta rows are written (Phi untouched)."""
+        import torch
+        B = uv.shape[0] if uv.dim() == 4 else -1
+        _need(uv, torch.float64, (B, 2, self.params.nlat, self.params.nlon), "uv")
+        if out is None:
+            out = torch.empty((B, 2, self.nspec), dtype=torch.complex128, device=uv.device)
+        ptr, stride, Bo = self._vd_view(out, "vd")
+        if Bo != B:
+            raise ValueError(f"vd holds {Bo} pairs, uv {B}")
+        _check(self._lib.sh_uv_to_vortdiv(self._h, c_void_p(uv.data_ptr()), ptr, stride, B,
+                                          _stream_handle(stream)), "sh_uv_to_vortdiv")
         return out
 
     def autotune(self, S: int, stream=None) -> int:
