@@ -49,42 +49,64 @@ __device__ void fft_lds(double2* X, const double2* tw, int n, bool inverse) {
     }
 }
 
-// grid [B][nlat][nlon] -> Fw[m][j][c] for m <= T; row j scaled by rs[j]
-// (rs may be NULL: no scaling).
-__global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ grid, double* __restrict__ Fw,
-                                                     const double2* __restrict__ tw, const double* __restrict__ rs,
-                                                     int nlat, int nlon, int bits, int T, int C) {
-    extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
-    double2* tws = X + nlon;
-    const int row = blockIdx.x;  // b * nlat + j
-    const int b = row / nlat, j = row - b * nlat;
-    const double* src = grid + (long long)row * nlon;
-    // all loads of this thread issued before any store (one memory latency)
-    constexpr int kU = 8;
+// Load grid row `src` into X in bit-reversed order and run the forward FFT.
+__device__ void row_fft_forward(const double* __restrict__ src, double2* X, const double2* tws, int nlon, int bits) {
+    constexpr int kU = 8;  // all loads of a thread issued before its stores
     for (int k0 = 0; k0 < nlon; k0 += kU * 256) {
         double v[kU];
-        double2 t[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int k = k0 + u * 256 + threadIdx.x;
             v[u] = (k < nlon) ? src[k] : 0.0;
-            t[u] = (k < nlon / 2) ? tw[k] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int k = k0 + u * 256 + threadIdx.x;
             if (k < nlon) X[bitrev(k, bits)] = make_double2(v[u], 0.0);
-            if (k < nlon / 2) tws[k] = t[u];
         }
     }
     __syncthreads();
     fft_lds(X, tws, nlon, false);
-    const double inv = (rs ? rs[j] : 1.0) / nlon;
-    for (int m = threadIdx.x; m <= T; m += blockDim.x) {
-        const double2 v = X[m];
-        double* dst = Fw + ((long long)m * nlat + j) * C + 2 * b;
-        dst[0] = v.x * inv;
-        dst[1] = v.y * inv;
+}
+
+// Rows j and j' = nlat-1-j of field b (j < nlat/2) -> the Gauss-weighted
+// even and odd parts of their Fourier coefficients, for m <= T (T < 1024):
+//   EO[m][0][j][c] = w_j s_j (F_j + F_j')_m,  EO[m][1][j][c] = w_j s_j (F_j - F_j')_m,
+// F = (1/nlon) DFT, c = 2b + {0: re, 1: im}, s_j = rs[j] (rs may be NULL; it
+// is symmetric about the equator).  These are the B operands of the forward
+// Legendre contraction.
+__global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ grid, double* __restrict__ EO,
+                                                     const double2* __restrict__ tw, const double* __restrict__ wts,
+                                                     const double* __restrict__ rs, int nlat, int nlon, int bits,
+                                                     int T, int C) {
+    extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
+    double2* tws = X + nlon;
+    const int H = nlat >> 1;
+    const int b = blockIdx.x / H, j = blockIdx.x - b * H;
+    for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
+    row_fft_forward(grid + ((long long)b * nlat + j) * nlon, X, tws, nlon, bits);
+    constexpr int kM = 4;  // orders per thread: m = tid + 256 k
+    double2 f[kM];
+#pragma unroll
+    for (int k = 0; k < kM; ++k) {
+        const int m = threadIdx.x + 256 * k;
+        f[k] = (m <= T) ? X[m] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();  // X is reused for row j'
+    row_fft_forward(grid + ((long long)b * nlat + (nlat - 1 - j)) * nlon, X, tws, nlon, bits);
+    const double sc = wts[j] * (rs ? rs[j] : 1.0) / nlon;
+#pragma unroll
+    for (int k = 0; k < kM; ++k) {
+        const int m = threadIdx.x + 256 * k;
+        if (m <= T) {
+            const double2 g = X[m];
+            double* e = EO + (((long long)m * 2) * H + j) * C + 2 * b;
+            double* o = e + (long long)H * C;
+            e[0] = sc * (f[k].x + g.x);
+            e[1] = sc * (f[k].y + g.y);
+            o[0] = sc * (f[k].x - g.x);
+            o[1] = sc * (f[k].y - g.y);
+        }
     }
 }
 
@@ -132,138 +154,136 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
 // itself (34 MB at T256) is never stored: P follows from the three-term
 // recurrence P_n = a_n mu P_{n-1} - b_n P_{n-2}, restarted every kRun degrees
 // from exact host values, which keeps the FP64 recurrence error at a few ulp.
-constexpr int kRun = 64;         // degrees per restart run
-constexpr int kFwdRun = 128;     // degrees per forward workgroup (a multiple of kRun)
-constexpr int kPhase = 32;       // degrees generated per forward phase (two 16-row parity tiles)
-constexpr int kPD = kPhase + 1;  // LDS row length of a generated tile (odd: spreads banks)
-constexpr int kLatBlock = 64;    // latitudes generated per forward block
+constexpr int kRun = 32;         // degrees per restart row of the table
+constexpr int kInvRun = 64;      // degrees between the inverse's restarts (a multiple of kRun)
+constexpr int kFwdDeg = 32;      // degrees per forward run: two 16-row parity tiles
+constexpr int kFwdLat = 128;     // latitudes per generated forward block
+constexpr int kPtPitch = kFwdLat + 1;  // LDS row pitch of the generated tile (odd: spreads banks)
+constexpr int kFwdGroup = 2;     // runs of one order per forward workgroup
 
-// Forward work: one run of order m.  Inverse work: latitude tiles [t0, t1) of
-// the orders m and m2 = T - m (one wave each, m2 = -1 when m = T - m); run0,
-// run2 = first restart rows of the two orders.
+// Forward work: nrun consecutive 32-degree runs of order m from degree n0,
+// first restart row `row` (m = -1: an empty slot).  Inverse work: latitude
+// tiles [t0, t1) of the orders m and m2 = T - m (one wave each, m2 = -1 when
+// m = T - m); run0, run2 = first restart rows.
 struct LegRun {
-    int m, n0, row, pad;
+    int m, n0, row, nrun;
 };
 struct LegWork {
     int m, t0, t1, run0;
     int m2, run2;  // second order of the workgroup (T - m), or -1
 };
 
-// Forward: out[b][idx(m, n)] = sum_{j<H} P_n^m(mu_j) w_j (F_j +- F_j'), + for
-// n - m even, - for odd, over the degrees n0 .. n0 + kFwdRun - 1 of one run.
-// Staged once in LDS: the weighted even/odd Fourier blocks E, O [H][C], the
-// run's recurrence coefficients (zero beyond T) and the recurrence state of
-// every latitude.  Per phase of 32 degrees and block of kLatBlock latitudes,
-// the first kLatBlock threads generate P (one latitude each) into Pt[lat][d];
-// then wave w accumulates output tile w (row tile = degree parity within the
-// phase, 16 columns) on MFMA, k running over latitudes.  Columns
-// [c_off, c_off + C) of the Fourier block (row stride Cs), C <= 32.
+// value of v in lane l of the wave (l uniform)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Forward: out[b][idx(m, n)] = sum_{j<H} P_n^m(mu_j) EO[m][r][j][c], r the
+// parity of n - m (EO holds the Gauss-weighted even / odd Fourier parts),
+// over the runs of one work item.  Wave w = 2 h + r owns output tile (degree
+// parity r, column tile h) and keeps its B fragments, EO[m][r][j][c] for its
+// lane's column and latitudes j = 4 s + lane/16, in registers for the whole
+// work item (one latitude block; larger grids reload them per block).  Per
+// run the first kFwdLat threads generate the 32 degrees of their latitude
+// into Pt[d][lat] (pitch kPtPitch), one barrier, then every wave runs its 32
+// MFMA k-steps with A from Pt; the next run's restart values and recurrence
+// coefficients (lane d holds degree n0 + d + 1, broadcast by readlane) are
+// loaded before the MFMAs.  Columns [c_off, c_off + C) of EO (row stride Cs),
+// C <= 32.
 __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restrict__ runs,
                                                           const double* __restrict__ restart,
                                                           const double2* __restrict__ coef,
                                                           const double* __restrict__ mu,
-                                                          const double* __restrict__ wts,
-                                                          const double* __restrict__ Fw, double* __restrict__ spec,
-                                                          int T, int nlat, int H, int Cs, int c_off, int C) {
-    extern __shared__ double lds[];
+                                                          const double* __restrict__ EO, double* __restrict__ spec,
+                                                          int T, int H, int Cs, int c_off, int C) {
+    __shared__ double Pt[kFwdDeg * kPtPitch];
     const LegRun rn = runs[blockIdx.x];
-    const int m = rn.m, n0 = rn.n0;
+    if (rn.m < 0) return;  // padding slot of the XCD-ordered list
+    const int m = rn.m;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int r = wave & 1, h = wave >> 1;  // degree parity and column tile of this wave
+    const int col = h * 16 + i;
+    const bool cok = col < C;
     const long long so = spec_offset(T, m);
     const long long ns = nspec_of(T);
-    double* E = lds;                                  // [H][C]
-    double* O = E + H * C;                            // [H][C]
-    double* Pt = O + H * C;                           // [kLatBlock][kPD]
-    double2* st = reinterpret_cast<double2*>(Pt + kLatBlock * kPD);  // [H]: (P_{n-1}, P_n)
-    double* xs = reinterpret_cast<double*>(st + H);                  // [H]: mu_j
-    // coefficients of degree n0 + k: a separate LDS object, so that the
-    // compiler sees they cannot alias the generated tile
-    __shared__ double2 cf[kFwdRun + 1];
-    // staging: every thread issues kU loads before its stores (one latency)
-    constexpr int kU = 8;
-    for (int i0 = 0; i0 < H * C; i0 += kU * 256) {
-        double f1[kU], f2[kU], wj[kU];
+    const double* Bsrc = EO + ((long long)(m * 2 + r) * H) * Cs + c_off + min(col, C - 1);
+    const int nblk = (H + kFwdLat - 1) / kFwdLat;
+    const int nit = rn.nrun * nblk;  // (run, latitude block) iterations
+    const bool gen = tid < kFwdLat;
+    // prefetched inputs of the next iteration's generation
+    auto fetch = [&](int it, double& pm, double& pc, double& x, double2& ab) {
+        const int g = it / nblk, lb = (it - g * nblk) * kFwdLat;
+        const int j = lb + tid;
+        const bool ok = gen && j < H;
+        const long long row = rn.row + g;
+        pm = ok ? restart[(row * 2) * H + j] : 0.0;
+        pc = ok ? restart[(row * 2 + 1) * H + j] : 0.0;
+        x = ok ? mu[j] : 0.0;
+        const int nc = rn.n0 + kFwdDeg * g + (lane & 31) + 1;
+        ab = (nc <= T) ? coef[so + (nc - m)] : make_double2(0.0, 0.0);
+    };
+    double pm_n, pc_n, x_n;
+    double2 ab_n;
+    fetch(0, pm_n, pc_n, x_n, ab_n);
+    double bf[kFwdLat / 4];
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < nit; ++it) {
+        const int g = it / nblk, blk = it - g * nblk;
+        const int lb = blk * kFwdLat;
+        if (it == 0 || nblk > 1) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int idx = i0 + u * 256 + tid;
-            const bool ok = idx < H * C;
-            const int j = ok ? idx / C : 0, c = ok ? idx - j * C : 0;
-            f1[u] = ok ? Fw[((long long)m * nlat + j) * Cs + c_off + c] : 0.0;
-            f2[u] = ok ? Fw[((long long)m * nlat + (nlat - 1 - j)) * Cs + c_off + c] : 0.0;
-            wj[u] = ok ? wts[j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int idx = i0 + u * 256 + tid;
-            if (idx < H * C) {
-                E[idx] = wj[u] * (f1[u] + f2[u]);
-                O[idx] = wj[u] * (f1[u] - f2[u]);
+            for (int q = 0; q < kFwdLat / 4; ++q) {
+                const int j = lb + 4 * q + kq;
+                bf[q] = (j < H) ? Bsrc[(long long)j * Cs] : 0.0;
             }
         }
-    }
-    for (int j = tid; j < H; j += blockDim.x) {
-        st[j] = make_double2(restart[((long long)rn.row * 2) * H + j], restart[((long long)rn.row * 2 + 1) * H + j]);
-        xs[j] = mu[j];
-    }
-    for (int k = tid; k <= kFwdRun; k += blockDim.x)
-        cf[k] = (k >= 1 && n0 + k <= T) ? coef[so + (n0 + k - m)] : make_double2(0.0, 0.0);
-    const int nend = min(T, n0 + kFwdRun - 1);
-    const int lane = tid & 63, wave = tid >> 6;
-    const int row = lane & 15, kq = lane >> 4;
-    const int nct = (C + 15) / 16;       // column tiles (<= 2)
-    const int tl = wave;                 // this wave's output tile, if any
-    const bool has_tile = tl < 2 * nct;
-    const int r = tl & 1, h = tl >> 1;   // row tile (degree parity in the phase), column tile
-    const int col = h * 16 + row;        // B / D column of this lane
-    const bool cok = has_tile && col < C;
-    const double* Bm = r ? O : E;        // (ph - m) is even, so the parity of n - m is r
-    for (int ph = n0; ph <= nend; ph += kPhase) {
-        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        for (int lb = 0; lb < H; lb += kLatBlock) {
-            const int nl = min(kLatBlock, H - lb);
-            __syncthreads();  // staging done / previous block consumed
-            if (tid < nl) {
-                const int j = lb + tid;
-                const double x = xs[j];
-                double2 pc = st[j];
-                const int k0 = ph - n0;  // cf index of degree ph is k0; step n -> n+1 uses k + 1
+        if (it > 0) __syncthreads();  // the previous tile is consumed
+        if (gen) {
+            double pm = pm_n, pc = pc_n;
+            const double x = x_n;
+            const double2 ab = ab_n;
 #pragma unroll
-                for (int d = 0; d < kPhase; ++d) {
-                    Pt[tid * kPD + d] = (ph + d <= nend) ? pc.y : 0.0;
-                    const double2 ab = cf[min(k0 + d + 1, kFwdRun)];
-                    pc = make_double2(pc.y, fma(ab.x * x, pc.y, -ab.y * pc.x));
-                }
-                st[j] = pc;
-            }
-            __syncthreads();
-            {
-                // the block's 16 k-steps: all fragment reads first, then the MFMAs.
-                // A wave without a tile multiplies zeros; no branch around the
-                // MFMAs keeps the accumulators in place.
-                constexpr int kSteps = kLatBlock / 4;
-                double av[kSteps], bv[kSteps];
-#pragma unroll
-                for (int q = 0; q < kSteps; ++q) {
-                    const int lat = (q >> 2) * 16 + 4 * kq + (q & 3);  // < kLatBlock
-                    const bool lok = lat < nl;
-                    av[q] = (lok && has_tile) ? Pt[lat * kPD + 2 * row + r] : 0.0;
-                    bv[q] = (lok && cok) ? Bm[(lb + min(lat, nl - 1)) * C + col] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < kSteps; ++q) {
-                    if (q & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc1, 0, 0, 0);
-                    else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
-                }
+            for (int d = 0; d < kFwdDeg; ++d) {
+                Pt[d * kPtPitch + tid] = pc;  // zero beyond T (zero coefficients there) and beyond H
+                const double ca = readlane_f64(ab.x, d), cb = readlane_f64(ab.y, d);
+                const double nx = fma(ca * x, pc, -cb * pm);
+                pm = pc;
+                pc = nx;
             }
         }
-        // accumulator register rr of lane l holds D[4 rr + l/16][l % 16]
-        if (cok) {
-            const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
+        if (it + 1 < nit) fetch(it + 1, pm_n, pc_n, x_n, ab_n);
+        __syncthreads();
+        const double* Ap = Pt + (2 * i + r) * kPtPitch + kq;
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int n = ph + 2 * (4 * rr + kq) + r;
-                if (n <= nend) spec[((long long)b * ns + so + (n - m)) * 2 + ri] = acc0[rr] + acc1[rr];
+        for (int q0 = 0; q0 < kFwdLat / 4; q0 += 8) {
+            double av[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) av[u] = Ap[4 * (q0 + u)];
+            __builtin_amdgcn_sched_barrier(0);  // the chunk's reads ahead of its MFMAs
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bf[q0 + u], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bf[q0 + u + 1], acc1, 0, 0, 0);
             }
+        }
+        if (blk == nblk - 1) {
+            // accumulator register rr of lane l holds D[4 rr + l/16][l % 16]
+            const int n0 = rn.n0 + kFwdDeg * g;
+            if (cok) {
+                const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int n = n0 + 2 * (4 * rr + kq) + r;
+                    if (n <= T) spec[((long long)b * ns + so + (n - m)) * 2 + ri] = acc0[rr] + acc1[rr];
+                }
+            }
+            acc0 = v4d{0.0, 0.0, 0.0, 0.0};
+            acc1 = v4d{0.0, 0.0, 0.0, 0.0};
         }
     }
 }
@@ -318,11 +338,11 @@ __device__ __forceinline__ void inverse_order(const InvOrder& od, const double* 
         for (int d = 0; d < 8; ++d) cfn[d] = cf[kb + 8 + d + 1];  // < L + 16
         loadB(kb + 8, bn);
         __builtin_amdgcn_sched_barrier(0);  // keep the next k-step's reads ahead of this one's work
-        if ((kb & (kRun - 1)) == 0) {       // start of a run: exact restart values
+        if ((kb & (kInvRun - 1)) == 0) {    // start of a run: exact restart values
             pv = pv_n;
             cu = cu_n;
-            if (kb + kRun < L && jok) {
-                const int row = od.run0 + kb / kRun + 1;
+            if (kb + kInvRun < L && jok) {
+                const int row = od.run0 + (kb + kInvRun) / kRun;
                 pv_n = restart[((long long)row * 2) * H + j];
                 cu_n = restart[((long long)row * 2 + 1) * H + j];
             }
@@ -515,18 +535,6 @@ __global__ void __launch_bounds__(256) k_uv_spec_to_vd(const double2* __restrict
 
 constexpr size_t kLdsBytes = 96 * 1024;  // LDS per workgroup used by the Legendre kernels
 
-// LDS of the forward kernel besides E and O: generated tile, state, coefficients.
-size_t forward_fixed_lds(int H) {
-    return sizeof(double) * kLatBlock * kPD + (sizeof(double2) + sizeof(double)) * (size_t)H +
-           sizeof(double2) * (kFwdRun + 1);
-}
-// Largest column chunk (even, <= 32) whose LDS fits kLdsBytes.
-int forward_chunk(int H, int C) {
-    const size_t pt = forward_fixed_lds(H);
-    const size_t per_col = sizeof(double) * 2 * (size_t)H;
-    const int cc = (int)((kLdsBytes - pt) / per_col) & ~1;
-    return std::max(2, std::min(std::min(C, 32), cc));
-}
 // Inverse LDS: both orders' blocks (lengths T + 1 - m and m + 1, together
 // T + 2) and coefficient columns.
 size_t inverse_lds(int T, int w) {
@@ -555,16 +563,32 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
     std::vector<int> run_base;
     std::vector<double> restart = legendre_restarts(Tt, kRun, north, run_base);
     std::vector<double> lcoef = legendre_coefs(Tt);
-    // forward: one workgroup per run, longest orders first (they come first);
+    // forward: one workgroup per kFwdGroup consecutive 32-degree runs of an
+    // order.  Workgroups go to the eight
+    // XCDs round-robin by index, so slot s is filled from the queue of XCD
+    // s % 8, which holds the runs of the orders m = s (mod 8), longest orders
+    // first: all runs of an order share one XCD and its L2, where the order's
+    // Fourier block is read from HBM once.  Queues that run out early are
+    // padded with empty slots (m = -1).
     // inverse: four latitude tiles (one per wave) of one order.  One order
     // per workgroup: pairing m with T - m evens the work per wave but halves
     // the waves in flight, which measured slower (30 vs 26 us at T256)
+    constexpr int kXcd = 8;
+    std::vector<std::vector<LegRun>> q(kXcd);
+    for (int m = 0; m <= T; ++m) {
+        const int nr = (Tt - m) / kFwdDeg + 1;
+        for (int r = 0; r < nr; r += kFwdGroup)
+            q[m % kXcd].push_back(LegRun{m, m + kFwdDeg * r, run_base[m] + r * (kFwdDeg / kRun),
+                                         std::min(kFwdGroup, nr - r)});
+    }
+    size_t qmax = 0;
+    for (auto& v : q) qmax = std::max(qmax, v.size());
     std::vector<LegRun> tf;
+    for (size_t k = 0; k < qmax; ++k)
+        for (int x = 0; x < kXcd; ++x) tf.push_back(k < q[x].size() ? q[x][k] : LegRun{-1, 0, 0, 0});
+    while (!tf.empty() && tf.back().m < 0) tf.pop_back();
     std::vector<LegWork> ti;
     const int nl = (H + 15) / 16;
-    for (int m = 0; m <= T; ++m)
-        for (int r = 0; m + kFwdRun * r <= Tt; ++r)
-            tf.push_back(LegRun{m, m + kFwdRun * r, run_base[m] + r * (kFwdRun / kRun), 0});
     for (int m = 0; m <= T; ++m)
         for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m], -1, 0});
     t.T = Tt;
@@ -598,8 +622,8 @@ int fft_bits(int nlon) {
 // grid rows [nf][nlat][nlon] -> Fw (C = 2 nf columns), row scale rs or NULL
 int fft_forward(rexi_plan* pl, const double* grid, int nf, const double* rs, hipStream_t s) {
     const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_forward, dim3(nf * pl->nlat), dim3(256), lds, s, grid, pl->d_four, pl->d_twiddle, rs,
-                       pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
+    hipLaunchKernelGGL(k_fft_forward, dim3(nf * pl->nhalf), dim3(256), lds, s, grid, pl->d_four, pl->d_twiddle,
+                       pl->d_wts, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
@@ -612,16 +636,13 @@ int fft_inverse(rexi_plan* pl, double* grid, int nf, const double* rs, hipStream
     return REXI_OK;
 }
 
-// Fw (C columns) -> spec [C/2][nspec(t.T)]
+// EO (C columns) -> spec [C/2][nspec(t.T)], in launches of at most 32 columns
 int leg_forward(rexi_plan* pl, const LegTables& t, double* spec, int C, hipStream_t s) {
-    const int H = pl->nhalf;
     const double2* coef = reinterpret_cast<const double2*>(t.d_lcoef);
-    const int cc = forward_chunk(H, C);
-    for (int c0 = 0; c0 < C; c0 += cc) {
-        const int w = std::min(cc, C - c0);
-        const size_t lf = sizeof(double) * 2 * (size_t)H * w + forward_fixed_lds(H);
-        hipLaunchKernelGGL(k_legendre_forward, dim3(t.ntiles_f), dim3(256), lf, s, (const LegRun*)t.d_tiles_f,
-                           t.d_restart, coef, pl->d_mu, pl->d_wts, pl->d_four, spec, t.T, pl->nlat, H, C, c0, w);
+    for (int c0 = 0; c0 < C; c0 += 32) {
+        const int w = std::min(32, C - c0);
+        hipLaunchKernelGGL(k_legendre_forward, dim3(t.ntiles_f), dim3(256), 0, s, (const LegRun*)t.d_tiles_f,
+                           t.d_restart, coef, pl->d_mu, pl->d_four, spec, t.T, pl->nhalf, C, c0, w);
         REXI_HIP(hipGetLastError());
     }
     return REXI_OK;
@@ -691,8 +712,6 @@ int sh_setup(rexi_plan* pl) {
     const int fft_lds = (nlon + nlon / 2) * (int)sizeof(double2);
     REXI_HIP(hipFuncSetAttribute((const void*)k_fft_forward, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
     REXI_HIP(hipFuncSetAttribute((const void*)k_fft_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
-    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_forward, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kLdsBytes));
     REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kLdsBytes));
     REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
