@@ -54,7 +54,8 @@ struct LegTables {
     double* d_lcoef = nullptr;    // [nspec(T)][2]
     void* d_tiles_f = nullptr;    // forward runs
     void* d_tiles_i = nullptr;    // inverse work
-    int ntiles_f = 0, ntiles_i = 0;
+    int* d_seg = nullptr;         // inverse partial slots of order m: d_seg[m] .. d_seg[m+1]-1
+    int ntiles_f = 0, ntiles_i = 0, nslots = 0;
 };
 
 __host__ __device__ inline long long spec_offset(int T, int m) {
@@ -157,7 +158,7 @@ struct rexi_plan {
     double* d_mu = nullptr;       // northern Gauss nodes [nhalf]
     double* d_wts = nullptr;      // Gauss weights
     double* d_rcos = nullptr;     // 1 / cos(lat_j) [nlat]
-    double* d_four = nullptr;     // Fourier coefficients workspace [T+1][nlat][2B]
+    double* d_four = nullptr;     // Fourier workspace [slots][nlat][2B] (slots >= T+1)
     double2* d_twiddle = nullptr; // FFT twiddles
     double2* d_vspec = nullptr;   // vector transforms: [max_fields][nspec(T+1)]
 

@@ -110,28 +110,49 @@ __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ 
     }
 }
 
-// Fw[m][j][c] -> grid [B][nlat][nlon]; row j scaled by rs[j] (rs may be NULL)
-__global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ Fw, double* __restrict__ grid,
-                                                     const double2* __restrict__ tw, const double* __restrict__ rs,
-                                                     int nlat, int nlon, int bits, int T, int C) {
+// Fw -> grid [B][nlat][nlon]; row j scaled by rs[j] (rs may be NULL).  The
+// Fourier coefficient of order m <= T (T < 1024) is the sum of the partial
+// slots seg[m] .. seg[m+1]-1 of Fw[slot][j][c] (one per degree segment).
+__global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ Fw, const int* __restrict__ seg,
+                                                     double* __restrict__ grid, const double2* __restrict__ tw,
+                                                     const double* __restrict__ rs, int nlat, int nlon, int bits,
+                                                     int T, int C) {
     extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
     double2* tws = X + nlon;
     const int row = blockIdx.x;
     const int b = row / nlat, j = row - b * nlat;
     for (int k = threadIdx.x; k < nlon; k += blockDim.x) X[k] = make_double2(0.0, 0.0);
     for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
-    __syncthreads();
-    // spectrum of the real field: X[m] += F_m, X[n-m] += conj(F_m), X[0] = Re F_0
-    for (int m = threadIdx.x; m <= T; m += blockDim.x) {
-        const double* s = Fw + ((long long)m * nlat + j) * C + 2 * b;
-        if (m == 0) X[0] = make_double2(s[0], 0.0);
-        else X[m % nlon] = make_double2(s[0], s[1]);
+    constexpr int kM = 4;  // orders per thread: m = tid + 256 k
+    double2 f[kM];
+#pragma unroll
+    for (int k = 0; k < kM; ++k) {
+        const int m = threadIdx.x + 256 * k;
+        double2 v = make_double2(0.0, 0.0);
+        if (m <= T) {
+            for (int sl = seg[m]; sl < seg[m + 1]; ++sl) {
+                const double* p = Fw + ((long long)sl * nlat + j) * C + 2 * b;
+                v.x += p[0];
+                v.y += p[1];
+            }
+        }
+        f[k] = v;
     }
     __syncthreads();
-    for (int m = 1 + threadIdx.x; m <= T; m += blockDim.x) {
-        const double* s = Fw + ((long long)m * nlat + j) * C + 2 * b;
-        const int q = (nlon - m % nlon) % nlon;
-        X[q] = make_double2(X[q].x + s[0], X[q].y - s[1]);
+    // spectrum of the real field: X[m] = F_m, then X[n-m] += conj(F_m), X[0] = Re F_0
+#pragma unroll
+    for (int k = 0; k < kM; ++k) {
+        const int m = threadIdx.x + 256 * k;
+        if (m <= T) X[m % nlon] = (m == 0) ? make_double2(f[k].x, 0.0) : f[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kM; ++k) {
+        const int m = threadIdx.x + 256 * k;
+        if (m >= 1 && m <= T) {
+            const int q = (nlon - m % nlon) % nlon;
+            X[q] = make_double2(X[q].x + f[k].x, X[q].y - f[k].y);
+        }
     }
     __syncthreads();
     // bit-reverse permutation in place
@@ -156,6 +177,7 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
 // from exact host values, which keeps the FP64 recurrence error at a few ulp.
 constexpr int kRun = 32;         // degrees per restart row of the table
 constexpr int kInvRun = 64;      // degrees between the inverse's restarts (a multiple of kRun)
+constexpr int kInvSeg = 128;     // degrees per inverse work item (a multiple of kInvRun)
 constexpr int kFwdDeg = 32;      // degrees per forward run: two 16-row parity tiles
 constexpr int kFwdLat = 128;     // latitudes per generated forward block
 constexpr int kPtPitch = kFwdLat + 1;  // LDS row pitch of the generated tile (odd: spreads banks)
@@ -163,14 +185,14 @@ constexpr int kFwdGroup = 2;     // runs of one order per forward workgroup
 
 // Forward work: nrun consecutive 32-degree runs of order m from degree n0,
 // first restart row `row` (m = -1: an empty slot).  Inverse work: latitude
-// tiles [t0, t1) of the orders m and m2 = T - m (one wave each, m2 = -1 when
-// m = T - m); run0, run2 = first restart rows.
+// tiles [t0, t1) of order m (one wave each) over the degree segment
+// m + n0 .. m + n0 + kInvSeg - 1, written to partial slot `slot`.
 struct LegRun {
     int m, n0, row, nrun;
 };
 struct LegWork {
-    int m, t0, t1, run0;
-    int m2, run2;  // second order of the workgroup (T - m), or -1
+    int m, t0, t1, run0;  // order, latitude tiles [t0, t1), restart row of degree m + n0
+    int n0, slot;         // first degree (offset from m) of the segment, output slot
 };
 
 // value of v in lane l of the wave (l uniform)
@@ -288,137 +310,42 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
     }
 }
 
-// Inverse: Fw[m][j] = Fe + Fo, Fw[m][j'] = Fe - Fo with Fe / Fo the sums of
-// P_n^m(mu_j) S_n over n - m even / odd.  A workgroup takes the orders m and
-// T - m together (their lengths add up to T + 2, which evens out the work),
-// stages both spectral blocks Sm [L][C] and coefficient columns in LDS, and
-// each wave owns 16 latitudes.  Lanes (i = lane & 15, kq = lane >> 4) run the
-// recurrence of latitude i in registers (the four kq lanes alike) and keep
-// what their MFMA fragment needs: per k-step of 8 degrees base .. base + 7,
-// A_even = P_{base + 2 kq}, A_odd = P_{base + 2 kq + 1}.  The coefficients and
-// B fragments of the next k-step are read while the current one is worked on.
-struct InvOrder {
-    int m, run0;
-    const double* Sm;   // [L][C] in LDS
-    const double2* cf;  // [L + 16] in LDS: coefficients of degree m + k (zero outside 1 <= k < L)
-};
+// Inverse: over one degree segment of order m, Fw[slot][j] = Fe + Fo,
+// Fw[slot][j'] = Fe - Fo with Fe / Fo the sums of P_n^m(mu_j) S_n over the
+// segment's n with n - m even / odd (the inverse FFT adds the segments of an
+// order).  Segments of at most kInvSeg degrees bound the serial work of a wave
+// and the block a workgroup stages.  A workgroup takes up to four 16-latitude
+// tiles (one wave each) and stages in LDS the segment's spectral block
+// Sm [Ls][C], its coefficient column and the exact restart values of its 64
+// latitudes at every kInvRun-th degree.  Lanes (i = lane & 15, kq = lane >> 4)
+// run the recurrence of latitude i in registers (the four kq lanes alike) and
+// keep what their MFMA fragment needs: per k-step of 8 degrees
+// base .. base + 7, A_even = P_{base + 2 kq}, A_odd = P_{base + 2 kq + 1}.
+// Degrees past the segment need no checks: their coefficients are zero, so P
+// is zero there, and the B reads are clamped into the block.  (Summing a
+// half-empty second column tile on the VALU instead of the MFMA pipe measured
+// slower: 22.3 vs 21.0 us at T256, 24 columns.)
 
-template <int NCT>
-__device__ __forceinline__ void inverse_order(const InvOrder& od, const double* __restrict__ restart,
-                                              double* __restrict__ Fw, int T, int nlat, int H, int Cs, int c_off,
-                                              int C, int t, int lane, double x, bool jok) {
-    const int m = od.m, L = T + 1 - m;
-    const int i = lane & 15, kq = lane >> 4;
-    const int j = t * 16 + i;
-    constexpr int nct = NCT;  // column tiles (C <= 16 NCT)
-    const double* Sm = od.Sm;
-    const double2* cf = od.cf;
-    auto loadB = [&](int kb, double* b) {  // be, bo of column tiles 0 and 1
-        const int de = kb + 2 * kq, dodd = de + 1;
-        const int c0 = i, c1 = 16 + i;
-        const int e_r = min(de, L - 1), o_r = min(dodd, L - 1);
-        b[0] = (de < L && c0 < C) ? Sm[e_r * C + min(c0, C - 1)] : 0.0;
-        b[1] = (dodd < L && c0 < C) ? Sm[o_r * C + min(c0, C - 1)] : 0.0;
-        b[2] = (de < L && c1 < C) ? Sm[e_r * C + min(c1, C - 1)] : 0.0;
-        b[3] = (dodd < L && c1 < C) ? Sm[o_r * C + min(c1, C - 1)] : 0.0;
-    };
-    v4d ae0 = {0.0, 0.0, 0.0, 0.0}, ao0 = ae0, ae1 = ae0, ao1 = ae0;
-    double pv = 0.0, cu = 0.0;
-    double pv_n = jok ? restart[((long long)od.run0 * 2) * H + j] : 0.0;
-    double cu_n = jok ? restart[((long long)od.run0 * 2 + 1) * H + j] : 0.0;
-    double2 cfv[8];
-    double bv[4];
+// Stage the spectral block of degrees m + n0 .. m + n0 + Ls - 1 ([Ls][C],
+// columns c_off..) and its coefficient column ([Ls + 16], cf[k] for degree
+// m + n0 + k, zero outside 1 <= k < Ls).  The coefficients of one field form
+// a contiguous run of 2 Ls <= 256 doubles: thread k takes double k of every
+// field (coalesced), all loads before the stores.
+__device__ __forceinline__ void stage_segment(long long so, long long ns, int Ls, int C, int c_off,
+                                              const double* __restrict__ spec, const double2* __restrict__ coef,
+                                              double* Sm, double2* cf) {
+    const int k = threadIdx.x;
+    const int nb = C >> 1;  // fields of this column chunk (C even, c_off even), <= 16
+    const bool ok = k < 2 * Ls;
+    double v[16];
 #pragma unroll
-    for (int d = 0; d < 8; ++d) cfv[d] = cf[d + 1];
-    loadB(0, bv);
-    for (int kb = 0; kb < L; kb += 8) {
-        double2 cfn[8];
-        double bn[4];
+    for (int f = 0; f < 16; ++f)
+        v[f] = (ok && f < nb) ? spec[((long long)((c_off >> 1) + f) * ns + so) * 2 + k] : 0.0;
 #pragma unroll
-        for (int d = 0; d < 8; ++d) cfn[d] = cf[kb + 8 + d + 1];  // < L + 16
-        loadB(kb + 8, bn);
-        __builtin_amdgcn_sched_barrier(0);  // keep the next k-step's reads ahead of this one's work
-        if ((kb & (kInvRun - 1)) == 0) {    // start of a run: exact restart values
-            pv = pv_n;
-            cu = cu_n;
-            if (kb + kInvRun < L && jok) {
-                const int row = od.run0 + (kb + kInvRun) / kRun;
-                pv_n = restart[((long long)row * 2) * H + j];
-                cu_n = restart[((long long)row * 2 + 1) * H + j];
-            }
-        }
-        double a_e = 0.0, a_o = 0.0;
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const double v = (kb + d < L) ? cu : 0.0;
-            if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? v : a_e;
-            else a_o = (kq == (d >> 1)) ? v : a_o;
-            const double nx = fma(cfv[d].x * x, cu, -cfv[d].y * pv);
-            pv = cu;
-            cu = nx;
-        }
-        ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, bv[0], ae0, 0, 0, 0);
-        ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bv[1], ao0, 0, 0, 0);
-        if constexpr (NCT > 1) {
-            ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, bv[2], ae1, 0, 0, 0);
-            ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, bv[3], ao1, 0, 0, 0);
-        }
-#pragma unroll
-        for (int d = 0; d < 8; ++d) cfv[d] = cfn[d];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bv[q] = bn[q];
-    }
-    // accumulator register q of lane l holds D[4 q + l/16][l % 16]: latitude
-    // row 4 q + kq of the tile, column l % 16 of the column tile
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-        const int col = hh * 16 + i;
-        if (hh >= nct || col >= C) continue;
-        const v4d ae = hh ? ae1 : ae0, ao = hh ? ao1 : ao0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int jj = t * 16 + 4 * q + kq;
-            if (jj < H) {
-                Fw[((long long)m * nlat + jj) * Cs + c_off + col] = ae[q] + ao[q];
-                Fw[((long long)m * nlat + (nlat - 1 - jj)) * Cs + c_off + col] = ae[q] - ao[q];
-            }
-        }
-    }
-}
-
-// Stage the spectral block of order m ([L][C], columns c_off..) and its
-// coefficient column ([L + 16]) into LDS.  The coefficients of one field and
-// order are contiguous in memory (2L doubles), so threads walk them field by
-// field (coalesced reads) and transpose into [d][c] in LDS; every thread
-// issues its loads before its stores.
-__device__ __forceinline__ void stage_order(int m, int T, int C, int c_off, const double* __restrict__ spec,
-                                            const double2* __restrict__ coef, double* Sm, double2* cf) {
-    const long long so = spec_offset(T, m);
-    const long long ns = nspec_of(T);
-    const int L = T + 1 - m;
-    const int L2 = 2 * L;  // doubles per field (re, im interleaved)
-    const int nb = C / 2;  // fields of this column chunk (C even, c_off even)
-    constexpr int kU = 8;
-    for (int i0 = 0; i0 < nb * L2; i0 += kU * 256) {
-        double v[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int idx = i0 + u * 256 + threadIdx.x;
-            const bool ok = idx < nb * L2;
-            const int f = ok ? idx / L2 : 0, k = ok ? idx - f * L2 : 0;
-            v[u] = ok ? spec[((long long)((c_off >> 1) + f) * ns + so) * 2 + k] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int idx = i0 + u * 256 + threadIdx.x;
-            if (idx < nb * L2) {
-                const int f = idx / L2, k = idx - f * L2;
-                Sm[(k >> 1) * C + 2 * f + (k & 1)] = v[u];  // degree d = k/2, column 2f + re/im
-            }
-        }
-    }
-    for (int k = threadIdx.x; k < L + 16; k += blockDim.x)
-        cf[k] = (k >= 1 && k < L) ? coef[so + k] : make_double2(0.0, 0.0);
+    for (int f = 0; f < 16; ++f)
+        if (ok && f < nb) Sm[(k >> 1) * C + 2 * f + (k & 1)] = v[f];  // degree k/2, column 2f + re/im
+    for (int q = threadIdx.x; q < Ls + 16; q += blockDim.x)
+        cf[q] = (q >= 1 && q < Ls) ? coef[so + q] : make_double2(0.0, 0.0);
 }
 
 template <int NCT>
@@ -431,31 +358,77 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
                                                           int c_off, int C) {
     extern __shared__ double lds[];
     const LegWork wk = work[blockIdx.x];
-    const int L0 = T + 1 - wk.m;
-    InvOrder o0, o1;
-    o0.m = wk.m;
-    o0.run0 = wk.run0;
-    o0.Sm = lds;
-    o0.cf = reinterpret_cast<const double2*>(lds + L0 * C);  // L0 * C is even (C is)
-    stage_order(o0.m, T, C, c_off, spec, coef, lds, reinterpret_cast<double2*>(lds + L0 * C));
-    if (wk.m2 >= 0) {
-        double* p = lds + L0 * C + 2 * (L0 + 16);
-        const int L1 = T + 1 - wk.m2;
-        o1.m = wk.m2;
-        o1.run0 = wk.run2;
-        o1.Sm = p;
-        o1.cf = reinterpret_cast<const double2*>(p + L1 * C);
-        stage_order(o1.m, T, C, c_off, spec, coef, p, reinterpret_cast<double2*>(p + L1 * C));
+    const int m = wk.m;
+    const int Ls = min(kInvSeg, T + 1 - m - wk.n0);  // degrees of this segment
+    const int nr = (Ls + kInvRun - 1) / kInvRun;       // restarts of this segment
+    double* Sm = lds;                                        // [Ls][C]
+    double2* cf = reinterpret_cast<double2*>(lds + Ls * C);  // [Ls + 16] (Ls * C is even: C is)
+    double* Rs = lds + Ls * C + 2 * (Ls + 16);               // [nr][2][64]
+    stage_segment(spec_offset(T, m) + wk.n0, nspec_of(T), Ls, C, c_off, spec, coef, Sm, cf);
+    const int jw = wk.t0 * 16;  // first latitude of the workgroup
+    for (int k = threadIdx.x; k < nr * 128; k += blockDim.x) {
+        const int r = k >> 7, w = (k >> 6) & 1, j = min(jw + (k & 63), H - 1);
+        Rs[k] = restart[((long long)(wk.run0 + r * (kInvRun / kRun)) * 2 + w) * H + j];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t = wk.t0 + wave;
     if (t >= wk.t1) return;  // no latitude tile for this wave (no barrier follows)
-    const int j = t * 16 + (lane & 15);
-    const bool jok = j < H;
-    const double x = jok ? mu[j] : 0.0;
-    inverse_order<NCT>(o0, restart, Fw, T, nlat, H, Cs, c_off, C, t, lane, x, jok);
-    if (wk.m2 >= 0) inverse_order<NCT>(o1, restart, Fw, T, nlat, H, Cs, c_off, C, t, lane, x, jok);
+    const int i = lane & 15, kq = lane >> 4;
+    const int j = t * 16 + i;
+    const double x = (j < H) ? mu[j] : 0.0;
+    const int c0 = min(i, C - 1), c1 = min(16 + i, C - 1);
+    v4d ae0 = {0.0, 0.0, 0.0, 0.0}, ao0 = ae0, ae1 = ae0, ao1 = ae0;
+    for (int r = 0; r < nr; ++r) {
+        double pv = Rs[(r * 2) * 64 + wave * 16 + i];
+        double cu = Rs[(r * 2 + 1) * 64 + wave * 16 + i];
+        const int kr = r * kInvRun;
+#pragma unroll
+        for (int ks = 0; ks < kInvRun; ks += 8) {
+            const int kb = kr + ks;
+            if (kb >= Ls) break;
+            double2 cv[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) cv[d] = cf[kb + d + 1];  // < Ls + 16
+            const int de = min(kb + 2 * kq, Ls - 1), dd = min(kb + 2 * kq + 1, Ls - 1);
+            const double b0 = Sm[de * C + c0], b1 = Sm[dd * C + c0];
+            const double b2 = Sm[de * C + c1], b3 = Sm[dd * C + c1];
+            double a_e = 0.0, a_o = 0.0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? cu : a_e;
+                else a_o = (kq == (d >> 1)) ? cu : a_o;
+                const double nx = fma(cv[d].x * x, cu, -cv[d].y * pv);
+                pv = cu;
+                cu = nx;
+            }
+            ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, b0, ae0, 0, 0, 0);
+            ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, b1, ao0, 0, 0, 0);
+            if constexpr (NCT > 1) {
+                ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, b2, ae1, 0, 0, 0);
+                ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, b3, ao1, 0, 0, 0);
+            }
+        }
+    }
+    // accumulator register q of lane l holds D[4 q + l/16][l % 16]: latitude
+    // row 4 q + kq of the tile, column l % 16 of the column tile
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int col = hh * 16 + i;
+        if (hh >= NCT || col >= C) continue;
+        const v4d ae = hh ? ae1 : ae0, ao = hh ? ao1 : ao0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = t * 16 + 4 * q + kq;
+            if (jj < H) {
+                // streaming stores: the partials go out while the kernel runs
+                // instead of as dirty L2 lines written back at its end
+                __builtin_nontemporal_store(ae[q] + ao[q], Fw + ((long long)wk.slot * nlat + jj) * Cs + c_off + col);
+                __builtin_nontemporal_store(ae[q] - ao[q],
+                                            Fw + ((long long)wk.slot * nlat + (nlat - 1 - jj)) * Cs + c_off + col);
+            }
+        }
+    }
 }
 
 // Vector transforms (Eq. (1): V = k x grad(psi) + grad(chi), lap psi = zeta,
@@ -533,17 +506,11 @@ __global__ void __launch_bounds__(256) k_uv_spec_to_vd(const double2* __restrict
     z[nspec_of(T)] = make_double2(dr * ia, di * ia);
 }
 
-constexpr size_t kLdsBytes = 96 * 1024;  // LDS per workgroup used by the Legendre kernels
 
-// Inverse LDS: both orders' blocks (lengths T + 1 - m and m + 1, together
-// T + 2) and coefficient columns.
-size_t inverse_lds(int T, int w) {
-    return sizeof(double) * (size_t)(T + 2) * w + sizeof(double2) * (size_t)(T + 2 + 32);
-}
-int inverse_chunk(int T, int C) {
-    const size_t cfb = sizeof(double2) * (T + 2 + 32);
-    const int cc = (int)((kLdsBytes - cfb) / (sizeof(double) * (T + 2))) & ~1;
-    return std::max(2, std::min(std::min(C, 32), cc));
+// Inverse LDS: a segment's block [kInvSeg][w], coefficient column and restart
+// values (2 x 64 latitudes per kInvRun degrees).
+size_t inverse_lds(int w) {
+    return sizeof(double) * ((size_t)kInvSeg * w + 2 * (size_t)(kInvSeg + 16) + (size_t)(kInvSeg / kInvRun) * 128);
 }
 
 }  // namespace
@@ -589,25 +556,38 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
     while (!tf.empty() && tf.back().m < 0) tf.pop_back();
     std::vector<LegWork> ti;
     const int nl = (H + 15) / 16;
-    for (int m = 0; m <= T; ++m)
-        for (int t0 = 0; t0 < nl; t0 += 4) ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m], -1, 0});
+    // inverse: degree segments of kInvSeg, partial slot seg[m] + s; full
+    // segments first (the longest work), each with its latitude tile groups
+    std::vector<int> seg(T + 2, 0);
+    for (int m = 0; m <= T; ++m) seg[m + 1] = seg[m] + (Tt - m) / kInvSeg + 1;
+    for (int full = 1; full >= 0; --full)
+        for (int m = 0; m <= T; ++m)
+            for (int n0 = 0; m + n0 <= Tt; n0 += kInvSeg) {
+                if ((m + n0 + kInvSeg - 1 <= Tt) != (full == 1)) continue;
+                for (int t0 = 0; t0 < nl; t0 += 4)
+                    ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m] + n0 / kRun, n0,
+                                         seg[m] + n0 / kInvSeg});
+            }
+    t.nslots = seg[T + 1];
     t.T = Tt;
     int rc = device_alloc((void**)&t.d_restart, restart.size() * sizeof(double));
     if (!rc) rc = device_alloc((void**)&t.d_lcoef, lcoef.size() * sizeof(double));
     if (!rc) rc = device_alloc((void**)&t.d_tiles_f, tf.size() * sizeof(LegRun));
     if (!rc) rc = device_alloc((void**)&t.d_tiles_i, ti.size() * sizeof(LegWork));
+    if (!rc) rc = device_alloc((void**)&t.d_seg, seg.size() * sizeof(int));
     if (rc) return rc;
     REXI_HIP(hipMemcpy(t.d_restart, restart.data(), restart.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(t.d_lcoef, lcoef.data(), lcoef.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(t.d_tiles_f, tf.data(), tf.size() * sizeof(LegRun), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(t.d_tiles_i, ti.data(), ti.size() * sizeof(LegWork), hipMemcpyHostToDevice));
+    REXI_HIP(hipMemcpy(t.d_seg, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice));
     t.ntiles_f = (int)tf.size();
     t.ntiles_i = (int)ti.size();
     return REXI_OK;
 }
 
 void leg_release(LegTables& t) {
-    void* ptrs[] = {t.d_restart, t.d_lcoef, t.d_tiles_f, t.d_tiles_i};
+    void* ptrs[] = {t.d_restart, t.d_lcoef, t.d_tiles_f, t.d_tiles_i, t.d_seg};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     t = LegTables{};
@@ -628,10 +608,10 @@ int fft_forward(rexi_plan* pl, const double* grid, int nf, const double* rs, hip
     return REXI_OK;
 }
 
-int fft_inverse(rexi_plan* pl, double* grid, int nf, const double* rs, hipStream_t s) {
+int fft_inverse(rexi_plan* pl, const LegTables& t, double* grid, int nf, const double* rs, hipStream_t s) {
     const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_inverse, dim3(nf * pl->nlat), dim3(256), lds, s, pl->d_four, grid, pl->d_twiddle, rs,
-                       pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
+    hipLaunchKernelGGL(k_fft_inverse, dim3(nf * pl->nlat), dim3(256), lds, s, pl->d_four, t.d_seg, grid,
+                       pl->d_twiddle, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
@@ -648,22 +628,22 @@ int leg_forward(rexi_plan* pl, const LegTables& t, double* spec, int C, hipStrea
     return REXI_OK;
 }
 
-// spec [C/2][nspec(t.T)] -> Fw (C columns)
+// spec [C/2][nspec(t.T)] -> partial slots of Fw (C columns), in launches of
+// at most 32 columns
 int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hipStream_t s) {
     const int H = pl->nhalf;
     const double2* coef = reinterpret_cast<const double2*>(t.d_lcoef);
-    const int cc = inverse_chunk(t.T, C);
-    for (int c0 = 0; c0 < C; c0 += cc) {
-        const int w = std::min(cc, C - c0);
-        const size_t li = inverse_lds(t.T, w);
+    for (int c0 = 0; c0 < C; c0 += 32) {
+        const int w = std::min(32, C - c0);
+        const size_t li = inverse_lds(w);
+        const LegWork* wl = (const LegWork*)t.d_tiles_i;
+        const dim3 g(t.ntiles_i), b(256);
         if (w > 16)
-            hipLaunchKernelGGL(k_legendre_inverse<2>, dim3(t.ntiles_i), dim3(256), li, s,
-                               (const LegWork*)t.d_tiles_i, t.d_restart, coef, pl->d_mu, spec, pl->d_four, t.T,
-                               pl->nlat, H, C, c0, w);
+            hipLaunchKernelGGL(k_legendre_inverse<2>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec,
+                               pl->d_four, t.T, pl->nlat, H, C, c0, w);
         else
-            hipLaunchKernelGGL(k_legendre_inverse<1>, dim3(t.ntiles_i), dim3(256), li, s,
-                               (const LegWork*)t.d_tiles_i, t.d_restart, coef, pl->d_mu, spec, pl->d_four, t.T,
-                               pl->nlat, H, C, c0, w);
+            hipLaunchKernelGGL(k_legendre_inverse<1>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec,
+                               pl->d_four, t.T, pl->nlat, H, C, c0, w);
         REXI_HIP(hipGetLastError());
     }
     return REXI_OK;
@@ -700,7 +680,10 @@ int sh_setup(rexi_plan* pl) {
     if (!rc) rc = device_alloc((void**)&pl->d_wts, wn.size() * sizeof(double));
     if (!rc) rc = device_alloc((void**)&pl->d_rcos, rcos.size() * sizeof(double));
     if (!rc) rc = device_alloc((void**)&pl->d_twiddle, tw.size() * sizeof(double2));
-    if (!rc) rc = device_alloc((void**)&pl->d_four, (size_t)(T + 1) * nlat * 2 * pl->prm.max_fields * sizeof(double));
+    // Fourier workspace: the forward's even/odd parts of T + 1 orders, or the
+    // inverse's partial slots
+    const size_t nsl = std::max<size_t>(T + 1, std::max(pl->leg.nslots, pl->legv.nslots));
+    if (!rc) rc = device_alloc((void**)&pl->d_four, nsl * nlat * 2 * pl->prm.max_fields * sizeof(double));
     if (!rc && pl->prm.max_fields >= 2)
         rc = device_alloc((void**)&pl->d_vspec, (size_t)pl->prm.max_fields * nspec_of(T + 1) * sizeof(double2));
     if (rc) return rc;
@@ -712,10 +695,7 @@ int sh_setup(rexi_plan* pl) {
     const int fft_lds = (nlon + nlon / 2) * (int)sizeof(double2);
     REXI_HIP(hipFuncSetAttribute((const void*)k_fft_forward, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
     REXI_HIP(hipFuncSetAttribute((const void*)k_fft_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
-    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kLdsBytes));
-    REXI_HIP(hipFuncSetAttribute((const void*)k_legendre_inverse<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kLdsBytes));
+
     return REXI_OK;
 }
 
@@ -759,7 +739,7 @@ int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStr
         REXI_HIP(timed_begin(pl, REXI_KERNEL_LEGENDRE_INV, s));
         if ((rc = leg_inverse(pl, pl->leg, (const double*)in, C, s))) return rc;
         REXI_HIP(timed_end(pl, REXI_KERNEL_LEGENDRE_INV, s));
-        if ((rc = fft_inverse(pl, (double*)out, B, nullptr, s))) return rc;
+        if ((rc = fft_inverse(pl, pl->leg, (double*)out, B, nullptr, s))) return rc;
     }
     return REXI_OK;
 }
@@ -787,7 +767,7 @@ int sh_vec_run(rexi_plan* pl, const void* in, void* out, long long stride, int B
                            pl->prm.radius);
         REXI_HIP(hipGetLastError());
         if ((rc = leg_inverse(pl, pl->legv, (const double*)pl->d_vspec, C, s))) return rc;
-        if ((rc = fft_inverse(pl, (double*)out, 2 * B, pl->d_rcos, s))) return rc;
+        if ((rc = fft_inverse(pl, pl->legv, (double*)out, 2 * B, pl->d_rcos, s))) return rc;
     } else {
         if ((rc = fft_forward(pl, (const double*)in, 2 * B, pl->d_rcos, s))) return rc;
         if ((rc = leg_forward(pl, pl->legv, (double*)pl->d_vspec, C, s))) return rc;

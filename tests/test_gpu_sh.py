@@ -14,7 +14,8 @@ def _announce(request):
 
 
 @pytest.mark.parametrize("T,nlat,nlon,B", [(15, 16, 32, 2), (63, 64, 128, 3), (128, 128, 256, 6),
-                                           (256, 256, 512, 12), (20, 22, 64, 1), (63, 64, 128, 40)])
+                                           (256, 256, 512, 12), (20, 22, 64, 1), (63, 64, 128, 40),
+                                           (40, 44, 128, 13), (33, 36, 64, 9)])
 def test_transforms_match_oracle(T, nlat, nlon, B):
     import torch
     import paper_1812_03431_amd as rexi
