@@ -49,28 +49,15 @@ __device__ void fft_lds(double2* X, const double2* tw, int n, bool inverse) {
     }
 }
 
-// Load grid row `src` into X in bit-reversed order and run the forward FFT.
-__device__ void row_fft_forward(const double* __restrict__ src, double2* X, const double2* tws, int nlon, int bits) {
-    constexpr int kU = 8;  // all loads of a thread issued before its stores
-    for (int k0 = 0; k0 < nlon; k0 += kU * 256) {
-        double v[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int k = k0 + u * 256 + threadIdx.x;
-            v[u] = (k < nlon) ? src[k] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int k = k0 + u * 256 + threadIdx.x;
-            if (k < nlon) X[bitrev(k, bits)] = make_double2(v[u], 0.0);
-        }
-    }
-    __syncthreads();
-    fft_lds(X, tws, nlon, false);
-}
+// Two real rows share one complex FFT: with z = x + i y,
+//   X_m = (Z_m + conj(Z_{N-m})) / 2,  Y_m = (Z_m - conj(Z_{N-m})) / (2 i),
+// and for the inverse, Z = X + i Y of two Hermitian spectra transforms back to
+// x + i y.  Rows j and j' = nlat-1-j of a field are the pair in both
+// directions, which is also what the Legendre kernels' equatorial symmetry
+// needs.
 
-// Rows j and j' = nlat-1-j of field b (j < nlat/2) -> the Gauss-weighted
-// even and odd parts of their Fourier coefficients, for m <= T (T < 1024):
+// Rows j and j' (j < nlat/2) of field b -> the Gauss-weighted even and odd
+// parts of their Fourier coefficients, for m <= T (T < 1024):
 //   EO[m][0][j][c] = w_j s_j (F_j + F_j')_m,  EO[m][1][j][c] = w_j s_j (F_j - F_j')_m,
 // F = (1/nlon) DFT, c = 2b + {0: re, 1: im}, s_j = rs[j] (rs may be NULL; it
 // is symmetric about the equator).  These are the B operands of the forward
@@ -83,67 +70,85 @@ __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ 
     double2* tws = X + nlon;
     const int H = nlat >> 1;
     const int b = blockIdx.x / H, j = blockIdx.x - b * H;
-    for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
-    row_fft_forward(grid + ((long long)b * nlat + j) * nlon, X, tws, nlon, bits);
-    constexpr int kM = 4;  // orders per thread: m = tid + 256 k
-    double2 f[kM];
+    const double* xr = grid + ((long long)b * nlat + j) * nlon;
+    const double* yr = grid + ((long long)b * nlat + (nlat - 1 - j)) * nlon;
+    constexpr int kU = 8;  // all loads of a thread issued before its stores
+    for (int k0 = 0; k0 < nlon; k0 += kU * 256) {
+        double vx[kU], vy[kU];
+        double2 t[kU];
 #pragma unroll
-    for (int k = 0; k < kM; ++k) {
-        const int m = threadIdx.x + 256 * k;
-        f[k] = (m <= T) ? X[m] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();  // X is reused for row j'
-    row_fft_forward(grid + ((long long)b * nlat + (nlat - 1 - j)) * nlon, X, tws, nlon, bits);
-    const double sc = wts[j] * (rs ? rs[j] : 1.0) / nlon;
-#pragma unroll
-    for (int k = 0; k < kM; ++k) {
-        const int m = threadIdx.x + 256 * k;
-        if (m <= T) {
-            const double2 g = X[m];
-            double* e = EO + (((long long)m * 2) * H + j) * C + 2 * b;
-            double* o = e + (long long)H * C;
-            e[0] = sc * (f[k].x + g.x);
-            e[1] = sc * (f[k].y + g.y);
-            o[0] = sc * (f[k].x - g.x);
-            o[1] = sc * (f[k].y - g.y);
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * 256 + threadIdx.x;
+            vx[u] = (k < nlon) ? xr[k] : 0.0;
+            vy[u] = (k < nlon) ? yr[k] : 0.0;
+            t[u] = (k < nlon / 2) ? tw[k] : make_double2(0.0, 0.0);
         }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * 256 + threadIdx.x;
+            if (k < nlon) X[bitrev(k, bits)] = make_double2(vx[u], vy[u]);
+            if (k < nlon / 2) tws[k] = t[u];
+        }
+    }
+    __syncthreads();
+    fft_lds(X, tws, nlon, false);
+    const double sc = 0.5 * wts[j] * (rs ? rs[j] : 1.0) / nlon;
+    for (int m = threadIdx.x; m <= T; m += blockDim.x) {
+        const double2 z = X[m % nlon], w = X[(nlon - m % nlon) % nlon];
+        // 2 X_m = z + conj(w), 2 Y_m = -i (z - conj(w))
+        const double xr2 = z.x + w.x, xi2 = z.y - w.y;
+        const double yr2 = z.y + w.y, yi2 = w.x - z.x;
+        double* e = EO + (((long long)m * 2) * H + j) * C + 2 * b;
+        double* o = e + (long long)H * C;
+        e[0] = sc * (xr2 + yr2);
+        e[1] = sc * (xi2 + yi2);
+        o[0] = sc * (xr2 - yr2);
+        o[1] = sc * (xi2 - yi2);
     }
 }
 
-// Fw -> grid [B][nlat][nlon]; row j scaled by rs[j] (rs may be NULL).  The
-// Fourier coefficient of order m <= T (T < 1024) is the sum of the partial
-// slots seg[m] .. seg[m+1]-1 of Fw[slot][j][c] (one per degree segment).
+// Fw -> rows j and j' = nlat-1-j (j < nlat/2) of field b of the grid
+// [B][nlat][nlon], scaled by rs[j] (rs may be NULL).  The Fourier coefficient
+// of order m <= T (T < 1024) is the sum of the partial slots
+// seg[m] .. seg[m+1]-1 of Fw[slot][row][c] (one per degree segment).
 __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ Fw, const int* __restrict__ seg,
                                                      double* __restrict__ grid, const double2* __restrict__ tw,
                                                      const double* __restrict__ rs, int nlat, int nlon, int bits,
                                                      int T, int C) {
     extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
     double2* tws = X + nlon;
-    const int row = blockIdx.x;
-    const int b = row / nlat, j = row - b * nlat;
+    const int H = nlat >> 1;
+    const int b = blockIdx.x / H, j = blockIdx.x - b * H, j2 = nlat - 1 - j;
     for (int k = threadIdx.x; k < nlon; k += blockDim.x) X[k] = make_double2(0.0, 0.0);
     for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
     constexpr int kM = 4;  // orders per thread: m = tid + 256 k
-    double2 f[kM];
+    double2 f[kM], g[kM];  // coefficients of rows j and j'
 #pragma unroll
     for (int k = 0; k < kM; ++k) {
         const int m = threadIdx.x + 256 * k;
-        double2 v = make_double2(0.0, 0.0);
+        double2 v = make_double2(0.0, 0.0), w = v;
         if (m <= T) {
             for (int sl = seg[m]; sl < seg[m + 1]; ++sl) {
                 const double* p = Fw + ((long long)sl * nlat + j) * C + 2 * b;
+                const double* q = Fw + ((long long)sl * nlat + j2) * C + 2 * b;
                 v.x += p[0];
                 v.y += p[1];
+                w.x += q[0];
+                w.y += q[1];
             }
+            if (m == 0) v.y = w.y = 0.0;  // real fields: Re F_0
         }
         f[k] = v;
+        g[k] = w;
     }
     __syncthreads();
-    // spectrum of the real field: X[m] = F_m, then X[n-m] += conj(F_m), X[0] = Re F_0
+    // Z = X + i Y with X[m] = F_m, X[N-m] = conj(F_m) (and Y alike from G):
+    // Z[m] += F_m + i G_m, Z[N-m] += conj(F_m) + i conj(G_m); two passes, as
+    // orders past N/2 alias onto the same bins
 #pragma unroll
     for (int k = 0; k < kM; ++k) {
         const int m = threadIdx.x + 256 * k;
-        if (m <= T) X[m % nlon] = (m == 0) ? make_double2(f[k].x, 0.0) : f[k];
+        if (m <= T) X[m % nlon] = make_double2(f[k].x - g[k].y, f[k].y + g[k].x);
     }
     __syncthreads();
 #pragma unroll
@@ -151,7 +156,7 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
         const int m = threadIdx.x + 256 * k;
         if (m >= 1 && m <= T) {
             const int q = (nlon - m % nlon) % nlon;
-            X[q] = make_double2(X[q].x + f[k].x, X[q].y - f[k].y);
+            X[q] = make_double2(X[q].x + f[k].x + g[k].y, X[q].y - f[k].y + g[k].x);
         }
     }
     __syncthreads();
@@ -166,9 +171,16 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
     }
     __syncthreads();
     fft_lds(X, tws, nlon, true);
-    double* dst = grid + (long long)row * nlon;
+    double* dx = grid + ((long long)b * nlat + j) * nlon;
+    double* dy = grid + ((long long)b * nlat + j2) * nlon;
     const double sc = rs ? rs[j] : 1.0;
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) dst[k] = X[k].x * sc;
+    // streaming stores for the contiguous output rows (measured 22.3 -> 20.5 us
+    // at T256, 12 fields; scattered outputs elsewhere measured slower with them)
+    for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
+        const double2 z = X[k];
+        __builtin_nontemporal_store(z.x * sc, dx + k);
+        __builtin_nontemporal_store(z.y * sc, dy + k);
+    }
 }
 
 // Legendre contractions with P_n^m generated on the device.  The table
@@ -610,7 +622,7 @@ int fft_forward(rexi_plan* pl, const double* grid, int nf, const double* rs, hip
 
 int fft_inverse(rexi_plan* pl, const LegTables& t, double* grid, int nf, const double* rs, hipStream_t s) {
     const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_inverse, dim3(nf * pl->nlat), dim3(256), lds, s, pl->d_four, t.d_seg, grid,
+    hipLaunchKernelGGL(k_fft_inverse, dim3(nf * pl->nhalf), dim3(256), lds, s, pl->d_four, t.d_seg, grid,
                        pl->d_twiddle, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
