@@ -44,3 +44,38 @@ def test_round_trip_on_gpu():
     g = plan.sh_inverse(torch.from_numpy(u).to(dev))
     back = plan.sh_forward(g).cpu().numpy()
     assert np.max(np.abs(back - u)) / np.max(np.abs(u)) < 1e-13
+
+
+@pytest.mark.parametrize("T,nlat,nlon,B", [(300, 320, 1024, 3), (1, 2, 4, 1), (3, 4, 8, 2)])
+def test_transforms_match_oracle_more_grids(T, nlat, nlon, B):
+    # 160 northern latitudes: the forward kernel's two-block path; and the
+    # smallest grids the plan accepts
+    import torch
+    import paper_1812_03431_amd as rexi
+    dev = torch.device("cuda:0")
+    w = synth.Workload("sh", T=T, nlat=nlat, nlon=nlon, dt=3600.0, M=8, states=1)
+    plan = rexi.plan_for(w, max_fields=2 * B)
+    grid = synth.random_grid(nlat, nlon, B, T + 1)
+    got = plan.sh_forward(torch.from_numpy(grid).to(dev)).cpu().numpy()
+    want = osh.analysis(grid, T)
+    assert np.max(np.abs(got - want)) / np.max(np.abs(want)) < 1e-12
+    spec = synth.random_state(T, B, T + 2)[:, 0]
+    got_g = plan.sh_inverse(torch.from_numpy(np.ascontiguousarray(spec)).to(dev)).cpu().numpy()
+    want_g = osh.synthesis(spec, T, nlat, nlon)
+    assert np.max(np.abs(got_g - want_g)) / np.max(np.abs(want_g)) < 1e-12
+
+
+def test_round_trip_at_the_largest_grid():
+    # T1023 on 4096 x 2048: sh_forward(sh_inverse(s)) = s exactly (n < nlat,
+    # m < nlon/2), on the largest sizes the plan accepts
+    import torch
+    import paper_1812_03431_amd as rexi
+    dev = torch.device("cuda:0")
+    T, nlat, nlon = 1023, 2048, 4096
+    w = synth.Workload("max", T=T, nlat=nlat, nlon=nlon, dt=3600.0, M=8, states=1)
+    plan = rexi.plan_for(w, max_fields=2)
+    u = torch.from_numpy(synth.random_state(T, 1, 9).reshape(3, -1)[:2].copy()).to(dev)
+    g = plan.sh_inverse(u)
+    back = plan.sh_forward(g)
+    err = (back - u).abs().max().item() / u.abs().max().item()
+    assert err < 1e-11, err

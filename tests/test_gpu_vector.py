@@ -29,7 +29,8 @@ def _relmax(got, want):
 # the bump grid (T127, 256 x 128) and the benchmark grid (T256, 512 x 256)
 # among them; B pairs need 2 B <= max_fields
 @pytest.mark.parametrize("T,nlat,nlon,B", [(15, 16, 32, 1), (63, 64, 128, 3), (40, 44, 128, 5),
-                                           (127, 128, 256, 2), (256, 256, 512, 6), (20, 22, 64, 17)])
+                                           (127, 128, 256, 2), (256, 256, 512, 6), (20, 22, 64, 17),
+                                           (300, 320, 1024, 2), (1, 2, 4, 1)])
 def test_vector_transforms_match_oracle(T, nlat, nlon, B):
     import torch
     dev = torch.device("cuda:0")
