@@ -4,15 +4,18 @@
 // Synthesis: xi(mu_j, lam_k) = sum_m c_m Re( sum_n xi_n^m P_n^m(mu_j) e^{i m lam_k} ), c_0 = 1, c_m = 2
 // (the m = 0 term uses Re(xi_n^0)).
 //
-// Longitude: one workgroup per grid row runs a radix-2 FFT of length nlon in
-// LDS.  Latitude: per zonal order m the Legendre sum is a small dense
-// contraction (T+1-m degrees x nlat/2 latitudes x 2B real columns) and runs
-// on FP64 MFMA (v_mfma_f64_16x16x4f64).  Gauss latitudes are symmetric about
-// the equator and P_n^m(-mu) = (-1)^{n-m} P_n^m(mu), so only northern
-// latitudes are used and each sum splits into an even part (F_j + F_{j'}) and
-// an odd part (F_j - F_{j'}), j' = nlat-1-j.
+// Longitude: one workgroup per pair of grid rows j, j' = nlat-1-j runs one
+// radix-2 complex FFT of length nlon in LDS for both rows.  Latitude: per
+// zonal order m the Legendre sum is a small dense contraction (T+1-m degrees
+// x nlat/2 latitudes x 2B real columns) and runs on FP64 MFMA
+// (v_mfma_f64_16x16x4f64).  Gauss latitudes are symmetric about the equator
+// and P_n^m(-mu) = (-1)^{n-m} P_n^m(mu), so only northern latitudes are used
+// and each sum splits into an even part (F_j + F_{j'}) and an odd part
+// (F_j - F_{j'}).
 //
-// Workspace layout of the Fourier coefficients: Fw[m][j][c], c = 2b + {0: re, 1: im}.
+// Fourier workspace (c = 2b + {0: re, 1: im}): the analysis writes the
+// weighted even/odd parts EO[m][0|1][j][c], j < nlat/2; the synthesis writes
+// partial sums Fw[slot][j][c] of degree segments, which the inverse FFT adds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
