@@ -31,17 +31,19 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
-// In-place radix-2 decimation-in-time FFT of X[0..n) in LDS (input already
-// in bit-reversed order).  tw[k] = exp(-2 pi i k / n), k < n/2; conj for the
+// In-place radix-2 decimation-in-time FFTs of nb arrays X + f n, f < nb, in
+// LDS (input already in bit-reversed order), one stage at a time over all of
+// them; n = 2^bits.  tw[k] = exp(-2 pi i k / n), k < n/2; conj for the
 // inverse direction.
-__device__ void fft_lds(double2* X, const double2* tw, int n, bool inverse) {
-    for (int len = 2; len <= n; len <<= 1) {
-        const int half = len >> 1;
-        const int step = n / len;
-        for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
-            const int grp = t / half, pos = t - grp * half;
-            const int i = grp * len + pos, j = i + half;
-            double2 w = tw[pos * step];
+__device__ void fft_lds(double2* X, const double2* tw, int bits, int nb, bool inverse) {
+    const int n = 1 << bits, hb = bits - 1;
+    for (int lh = 0; lh < bits; ++lh) {  // butterfly half-length 2^lh
+        const int half = 1 << lh;
+        for (int t = threadIdx.x; t < (nb << hb); t += blockDim.x) {
+            const int f = t >> hb, tt = t & ((1 << hb) - 1);
+            const int grp = tt >> lh, pos = tt & (half - 1);
+            const int i = f * n + (grp << (lh + 1)) + pos, j = i + half;
+            double2 w = tw[pos << (hb - lh)];
             if (inverse) w.y = -w.y;
             const double2 u = X[i], v0 = X[j];
             const double2 v = make_double2(fma(w.x, v0.x, -w.y * v0.y), fma(w.x, v0.y, w.y * v0.x));
@@ -57,132 +59,143 @@ __device__ void fft_lds(double2* X, const double2* tw, int n, bool inverse) {
 // and for the inverse, Z = X + i Y of two Hermitian spectra transforms back to
 // x + i y.  Rows j and j' = nlat-1-j of a field are the pair in both
 // directions, which is also what the Legendre kernels' equatorial symmetry
-// needs.
+// needs.  A workgroup takes the pair for a group of up to nb fields, so that
+// the per-order outputs (forward) and inputs (inverse) of the group are
+// contiguous.
 
-// Rows j and j' (j < nlat/2) of field b -> the Gauss-weighted even and odd
-// parts of their Fourier coefficients, for m <= T (T < 1024):
+// Rows j and j' (j < nlat/2) of fields b0 .. b0+nbr-1 -> the Gauss-weighted
+// even and odd parts of their Fourier coefficients, for m <= T (T < nlon):
 //   EO[m][0][j][c] = w_j s_j (F_j + F_j')_m,  EO[m][1][j][c] = w_j s_j (F_j - F_j')_m,
 // F = (1/nlon) DFT, c = 2b + {0: re, 1: im}, s_j = rs[j] (rs may be NULL; it
 // is symmetric about the equator).  These are the B operands of the forward
-// Legendre contraction.
+// Legendre contraction.  Workgroup g H + j takes field group g.
 __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ grid, double* __restrict__ EO,
                                                      const double2* __restrict__ tw, const double* __restrict__ wts,
                                                      const double* __restrict__ rs, int nlat, int nlon, int bits,
-                                                     int T, int C) {
-    extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
-    double2* tws = X + nlon;
-    const int H = nlat >> 1;
-    const int b = blockIdx.x / H, j = blockIdx.x - b * H;
-    const double* xr = grid + ((long long)b * nlat + j) * nlon;
-    const double* yr = grid + ((long long)b * nlat + (nlat - 1 - j)) * nlon;
+                                                     int T, int C, int nb) {
+    extern __shared__ double2 X[];  // [nb][nlon] data, then [nlon/2] twiddles
+    const int H = nlat >> 1, nf = C >> 1;
+    const int g = blockIdx.x / H, j = blockIdx.x - g * H;
+    const int b0 = g * nb, nbr = min(nb, nf - b0);
+    double2* tws = X + nb * nlon;
+    for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
     constexpr int kU = 8;  // all loads of a thread issued before its stores
-    for (int k0 = 0; k0 < nlon; k0 += kU * 256) {
+    const int tot = nbr * nlon;
+    for (int k0 = 0; k0 < tot; k0 += kU * 256) {
         double vx[kU], vy[kU];
-        double2 t[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int k = k0 + u * 256 + threadIdx.x;
-            vx[u] = (k < nlon) ? xr[k] : 0.0;
-            vy[u] = (k < nlon) ? yr[k] : 0.0;
-            t[u] = (k < nlon / 2) ? tw[k] : make_double2(0.0, 0.0);
+            const int e = min(k0 + u * 256 + threadIdx.x, tot - 1);
+            const int f = e >> bits, k = e & (nlon - 1);
+            vx[u] = grid[((long long)(b0 + f) * nlat + j) * nlon + k];
+            vy[u] = grid[((long long)(b0 + f) * nlat + (nlat - 1 - j)) * nlon + k];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int k = k0 + u * 256 + threadIdx.x;
-            if (k < nlon) X[bitrev(k, bits)] = make_double2(vx[u], vy[u]);
-            if (k < nlon / 2) tws[k] = t[u];
+            const int e = k0 + u * 256 + threadIdx.x;
+            if (e < tot) {
+                const int f = e >> bits, k = e & (nlon - 1);
+                X[f * nlon + bitrev(k, bits)] = make_double2(vx[u], vy[u]);
+            }
         }
     }
     __syncthreads();
-    fft_lds(X, tws, nlon, false);
+    fft_lds(X, tws, bits, nbr, false);
     const double sc = 0.5 * wts[j] * (rs ? rs[j] : 1.0) / nlon;
     for (int m = threadIdx.x; m <= T; m += blockDim.x) {
-        const double2 z = X[m % nlon], w = X[(nlon - m % nlon) % nlon];
-        // 2 X_m = z + conj(w), 2 Y_m = -i (z - conj(w))
-        const double xr2 = z.x + w.x, xi2 = z.y - w.y;
-        const double yr2 = z.y + w.y, yi2 = w.x - z.x;
-        double* e = EO + (((long long)m * 2) * H + j) * C + 2 * b;
+        double* e = EO + (((long long)m * 2) * H + j) * C + 2 * b0;
         double* o = e + (long long)H * C;
-        e[0] = sc * (xr2 + yr2);
-        e[1] = sc * (xi2 + yi2);
-        o[0] = sc * (xr2 - yr2);
-        o[1] = sc * (xi2 - yi2);
+        for (int f = 0; f < nbr; ++f) {
+            const double2 z = X[f * nlon + m], w = X[f * nlon + (nlon - m) % nlon];
+            // 2 X_m = z + conj(w), 2 Y_m = -i (z - conj(w))
+            const double xr2 = z.x + w.x, xi2 = z.y - w.y;
+            const double yr2 = z.y + w.y, yi2 = w.x - z.x;
+            e[2 * f] = sc * (xr2 + yr2);
+            e[2 * f + 1] = sc * (xi2 + yi2);
+            o[2 * f] = sc * (xr2 - yr2);
+            o[2 * f + 1] = sc * (xi2 - yi2);
+        }
     }
 }
 
-// Fw -> rows j and j' = nlat-1-j (j < nlat/2) of field b of the grid
-// [B][nlat][nlon], scaled by rs[j] (rs may be NULL).  The Fourier coefficient
-// of order m <= T (T < 1024) is the sum of the partial slots
+// Fw -> rows j and j' = nlat-1-j (j < nlat/2) of fields b0 .. b0+nbr-1 of the
+// grid [B][nlat][nlon], scaled by rs[j] (rs may be NULL).  The Fourier
+// coefficient of order m <= T (T < 1024) is the sum of the partial slots
 // seg[m] .. seg[m+1]-1 of Fw[slot][row][c] (one per degree segment).
 __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ Fw, const int* __restrict__ seg,
                                                      double* __restrict__ grid, const double2* __restrict__ tw,
                                                      const double* __restrict__ rs, int nlat, int nlon, int bits,
-                                                     int T, int C) {
-    extern __shared__ double2 X[];  // [nlon] data, then [nlon/2] twiddles
-    double2* tws = X + nlon;
-    const int H = nlat >> 1;
-    const int b = blockIdx.x / H, j = blockIdx.x - b * H, j2 = nlat - 1 - j;
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) X[k] = make_double2(0.0, 0.0);
+                                                     int T, int C, int nb) {
+    extern __shared__ double2 X[];  // [nb][nlon] data, then [nlon/2] twiddles
+    const int H = nlat >> 1, nf = C >> 1;
+    const int g = blockIdx.x / H, j = blockIdx.x - g * H, j2 = nlat - 1 - j;
+    const int b0 = g * nb, nbr = min(nb, nf - b0);
+    double2* tws = X + nb * nlon;
+    for (int k = threadIdx.x; k < nb * nlon; k += blockDim.x) X[k] = make_double2(0.0, 0.0);
     for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
-    constexpr int kM = 4;  // orders per thread: m = tid + 256 k
-    double2 f[kM], g[kM];  // coefficients of rows j and j'
+    __syncthreads();
+    for (int f = 0; f < nbr; ++f) {
+        double2* Xf = X + f * nlon;
+        const int cb = 2 * (b0 + f);
+        constexpr int kM = 4;  // orders per thread: m = tid + 256 k
+        double2 fv[kM], gv[kM];  // coefficients of rows j and j'
 #pragma unroll
-    for (int k = 0; k < kM; ++k) {
-        const int m = threadIdx.x + 256 * k;
-        double2 v = make_double2(0.0, 0.0), w = v;
-        if (m <= T) {
-            for (int sl = seg[m]; sl < seg[m + 1]; ++sl) {
-                const double* p = Fw + ((long long)sl * nlat + j) * C + 2 * b;
-                const double* q = Fw + ((long long)sl * nlat + j2) * C + 2 * b;
-                v.x += p[0];
-                v.y += p[1];
-                w.x += q[0];
-                w.y += q[1];
+        for (int k = 0; k < kM; ++k) {
+            const int m = threadIdx.x + 256 * k;
+            double2 v = make_double2(0.0, 0.0), w = v;
+            if (m <= T) {
+                for (int sl = seg[m]; sl < seg[m + 1]; ++sl) {
+                    const double* p = Fw + ((long long)sl * nlat + j) * C + cb;
+                    const double* q = Fw + ((long long)sl * nlat + j2) * C + cb;
+                    v.x += p[0];
+                    v.y += p[1];
+                    w.x += q[0];
+                    w.y += q[1];
+                }
+                if (m == 0) v.y = w.y = 0.0;  // real fields: Re F_0
             }
-            if (m == 0) v.y = w.y = 0.0;  // real fields: Re F_0
+            fv[k] = v;
+            gv[k] = w;
         }
-        f[k] = v;
-        g[k] = w;
-    }
-    __syncthreads();
-    // Z = X + i Y with X[m] = F_m, X[N-m] = conj(F_m) (and Y alike from G):
-    // Z[m] += F_m + i G_m, Z[N-m] += conj(F_m) + i conj(G_m); two passes, as
-    // orders past N/2 alias onto the same bins
+        // Z = X + i Y with X[m] = F_m, X[N-m] = conj(F_m) (and Y alike from G):
+        // Z[m] += F_m + i G_m, Z[N-m] += conj(F_m) + i conj(G_m); two passes, as
+        // orders past N/2 alias onto the same bins
 #pragma unroll
-    for (int k = 0; k < kM; ++k) {
-        const int m = threadIdx.x + 256 * k;
-        if (m <= T) X[m % nlon] = make_double2(f[k].x - g[k].y, f[k].y + g[k].x);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kM; ++k) {
-        const int m = threadIdx.x + 256 * k;
-        if (m >= 1 && m <= T) {
-            const int q = (nlon - m % nlon) % nlon;
-            X[q] = make_double2(X[q].x + f[k].x + g[k].y, X[q].y - f[k].y + g[k].x);
+        for (int k = 0; k < kM; ++k) {
+            const int m = threadIdx.x + 256 * k;
+            if (m <= T) Xf[m % nlon] = make_double2(fv[k].x - gv[k].y, fv[k].y + gv[k].x);
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kM; ++k) {
+            const int m = threadIdx.x + 256 * k;
+            if (m >= 1 && m <= T) {
+                const int q = (nlon - m % nlon) % nlon;
+                Xf[q] = make_double2(Xf[q].x + fv[k].x + gv[k].y, Xf[q].y - fv[k].y + gv[k].x);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // bit-reverse permutation in place
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
+    for (int e = threadIdx.x; e < nbr * nlon; e += blockDim.x) {
+        const int f = e >> bits, k = e & (nlon - 1);
         const int r = bitrev(k, bits);
         if (r > k) {
-            const double2 t = X[k];
-            X[k] = X[r];
-            X[r] = t;
+            const double2 t = X[f * nlon + k];
+            X[f * nlon + k] = X[f * nlon + r];
+            X[f * nlon + r] = t;
         }
     }
     __syncthreads();
-    fft_lds(X, tws, nlon, true);
-    double* dx = grid + ((long long)b * nlat + j) * nlon;
-    double* dy = grid + ((long long)b * nlat + j2) * nlon;
+    fft_lds(X, tws, bits, nbr, true);
     const double sc = rs ? rs[j] : 1.0;
     // streaming stores for the contiguous output rows (measured 22.3 -> 20.5 us
     // at T256, 12 fields; scattered outputs elsewhere measured slower with them)
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
-        const double2 z = X[k];
-        __builtin_nontemporal_store(z.x * sc, dx + k);
-        __builtin_nontemporal_store(z.y * sc, dy + k);
+    for (int e = threadIdx.x; e < nbr * nlon; e += blockDim.x) {
+        const int f = e >> bits, k = e & (nlon - 1);
+        const double2 z = X[e];
+        __builtin_nontemporal_store(z.x * sc, grid + ((long long)(b0 + f) * nlat + j) * nlon + k);
+        __builtin_nontemporal_store(z.y * sc, grid + ((long long)(b0 + f) * nlat + j2) * nlon + k);
     }
 }
 
@@ -608,6 +621,8 @@ void leg_release(LegTables& t) {
     t = LegTables{};
 }
 
+constexpr size_t kFftLds = 96 * 1024;  // LDS allowance of the FFT kernels (nlon = 4096 needs 96 KB)
+
 int fft_bits(int nlon) {
     int bits = 0;
     while ((1 << bits) < nlon) ++bits;
@@ -615,18 +630,26 @@ int fft_bits(int nlon) {
 }
 
 // grid rows [nf][nlat][nlon] -> Fw (C = 2 nf columns), row scale rs or NULL
+// Fields per FFT workgroup.  One: the FFTs are latency-bound per workgroup,
+// and four fields per workgroup (contiguous per-order writes, a quarter of the
+// workgroups) measured slower at T256, 12 fields (22.4 / 30.7 us against
+// 16.5 / 20.9 us forward / inverse).
+int fft_group(const rexi_plan*, int) { return 1; }
+
 int fft_forward(rexi_plan* pl, const double* grid, int nf, const double* rs, hipStream_t s) {
-    const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_forward, dim3(nf * pl->nhalf), dim3(256), lds, s, grid, pl->d_four, pl->d_twiddle,
-                       pl->d_wts, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
+    const int nb = fft_group(pl, nf);
+    const size_t lds = (size_t)(nb * pl->nlon + pl->nlon / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_forward, dim3(((nf + nb - 1) / nb) * pl->nhalf), dim3(256), lds, s, grid, pl->d_four,
+                       pl->d_twiddle, pl->d_wts, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf, nb);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
 
 int fft_inverse(rexi_plan* pl, const LegTables& t, double* grid, int nf, const double* rs, hipStream_t s) {
-    const size_t lds = (size_t)(pl->nlon + pl->nlon / 2) * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_inverse, dim3(nf * pl->nhalf), dim3(256), lds, s, pl->d_four, t.d_seg, grid,
-                       pl->d_twiddle, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf);
+    const int nb = fft_group(pl, nf);
+    const size_t lds = (size_t)(nb * pl->nlon + pl->nlon / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_inverse, dim3(((nf + nb - 1) / nb) * pl->nhalf), dim3(256), lds, s, pl->d_four, t.d_seg,
+                       grid, pl->d_twiddle, rs, pl->nlat, pl->nlon, fft_bits(pl->nlon), pl->T, 2 * nf, nb);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
@@ -707,9 +730,8 @@ int sh_setup(rexi_plan* pl) {
     REXI_HIP(hipMemcpy(pl->d_rcos, rcos.data(), rcos.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(pl->d_twiddle, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
     // dynamic LDS above 64 KB per workgroup
-    const int fft_lds = (nlon + nlon / 2) * (int)sizeof(double2);
-    REXI_HIP(hipFuncSetAttribute((const void*)k_fft_forward, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
-    REXI_HIP(hipFuncSetAttribute((const void*)k_fft_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, fft_lds));
+    REXI_HIP(hipFuncSetAttribute((const void*)k_fft_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLds));
+    REXI_HIP(hipFuncSetAttribute((const void*)k_fft_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLds));
 
     return REXI_OK;
 }
