@@ -109,6 +109,25 @@ def test_step_chains_beyond_256_elements(torch_dev):
         assert_parity(got_a[:, :, mask], want_a[:, :, mask], what=f"T{T} adjoint schedule {i}")
 
 
+def test_step_at_the_largest_truncation(torch_dev):
+    # T1023, the largest truncation a plan accepts: chains of up to 1023
+    # elements over 64 lanes of 16 elements (ds_bpermute moves), forward and
+    # adjoint on sampled orders.  dt = 60 s keeps dt * omega_T near 3, inside
+    # h M = 6.4.
+    T, S, M, dt = 1023, 1, 32, 60.0
+    orders = [0, 1, 2, 511, 1021, 1022, 1023]
+    w = synth.Workload("tmax", T=T, nlat=0, nlon=0, dt=dt, M=M, states=S)
+    u0 = synth.random_state(T, S, 1023)
+    mask = block_mask(T, orders)
+    plan = _plan(w, grid=False)
+    got = plan.step(_gpu(u0, torch_dev)).cpu().numpy()
+    want = _oracle_step(u0, w, orders=orders)
+    assert_parity(got[:, :, mask], want[:, :, mask], what="T1023")
+    got_a = plan.step_adjoint(_gpu(u0, torch_dev)).cpu().numpy()
+    want_a = _oracle_step(u0, w, adjoint=True, orders=orders)
+    assert_parity(got_a[:, :, mask], want_a[:, :, mask], what="T1023 adjoint")
+
+
 def test_zero_steps_copy_the_state(torch_dev):
     w = synth.Workload("zero", T=20, nlat=0, nlon=0, dt=3600.0, M=16, states=2)
     plan = _plan(w, grid=False)
