@@ -99,3 +99,16 @@ def test_vector_argument_errors():
     one = _plan(T, nlat, nlon, 1)
     with pytest.raises(rexi.RexiError, match="max_fields"):
         one.vortdiv_to_uv(vd[:1])
+
+
+def test_vector_round_trip_at_the_largest_grid():
+    # T1023 on 4096 x 2048 (degree 1024 inside the transforms): the winds of a
+    # T-truncated state give the state back exactly, as nlat >= T + 1
+    import torch
+    dev = torch.device("cuda:0")
+    T, nlat, nlon = 1023, 2048, 4096
+    plan = _plan(T, nlat, nlon, 2)
+    vd = torch.from_numpy(np.ascontiguousarray(synth.random_state(T, 1, 5)[:, 1:])).to(dev)
+    back = plan.uv_to_vortdiv(plan.vortdiv_to_uv(vd))
+    err = (back - vd).abs().max().item() / vd.abs().max().item()
+    assert err < 1e-11, err
