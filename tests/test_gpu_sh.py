@@ -79,3 +79,42 @@ def test_round_trip_at_the_largest_grid():
     back = plan.sh_forward(g)
     err = (back - u).abs().max().item() / u.abs().max().item()
     assert err < 1e-11, err
+
+
+def _random_shapes(n, seed=2024):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    while len(out) < n:
+        nlon = int(2 ** rng.integers(2, 11))          # 4 .. 1024
+        T = int(rng.integers(1, min(nlon - 1, 200) + 1))
+        nlat = int(2 * rng.integers(1, 151))           # 2 .. 300, even
+        B = int(rng.integers(1, 21))
+        out.append((T, nlat, nlon, B))
+    return out
+
+
+@pytest.mark.parametrize("T,nlat,nlon,B", _random_shapes(16))
+def test_transforms_random_shapes(T, nlat, nlon, B):
+    # scalar and vector transforms on seeded random shapes (T above or below
+    # nlat, ragged column chunks) against the oracle
+    import torch
+    import paper_1812_03431_amd as rexi
+    dev = torch.device("cuda:0")
+    w = synth.Workload("rnd", T=T, nlat=nlat, nlon=nlon, dt=3600.0, M=8, states=1)
+    plan = rexi.plan_for(w, max_fields=2 * B)
+    grid = synth.random_grid(nlat, nlon, B, T + nlat)
+    got = plan.sh_forward(torch.from_numpy(grid).to(dev)).cpu().numpy()
+    want = osh.analysis(grid, T)
+    assert np.max(np.abs(got - want)) / np.max(np.abs(want)) < 1e-12
+    spec = synth.random_state(T, B, T + nlon)[:, 0]
+    got_g = plan.sh_inverse(torch.from_numpy(np.ascontiguousarray(spec)).to(dev)).cpu().numpy()
+    want_g = osh.synthesis(spec, T, nlat, nlon)
+    assert np.max(np.abs(got_g - want_g)) / np.max(np.abs(want_g)) < 1e-12
+    vd = synth.random_state(T, B, T + 7)[:, 1:]
+    uv = plan.vortdiv_to_uv(torch.from_numpy(np.ascontiguousarray(vd)).to(dev)).cpu().numpy()
+    want_uv = osh.vortdiv_to_uv(vd, T, nlat, nlon, synth.EARTH_RADIUS)
+    assert np.max(np.abs(uv - want_uv)) / np.max(np.abs(want_uv)) < 1e-11
+    winds = synth.random_grid(nlat, nlon, 2 * B, T + 9).reshape(B, 2, nlat, nlon)
+    got_vd = plan.uv_to_vortdiv(torch.from_numpy(winds).to(dev)).cpu().numpy()
+    want_vd = osh.uv_to_vortdiv(winds, T, synth.EARTH_RADIUS)
+    assert np.max(np.abs(got_vd - want_vd)) / np.max(np.abs(want_vd)) < 1e-11
