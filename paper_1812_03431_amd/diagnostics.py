@@ -1,0 +1,42 @@
+"""Physical-space diagnostics of spectral states (Eq. (1), Section 3).
+
+``grid_fields(plan, u)`` returns the geopotential perturbation Phi and the
+winds (u, v) of states [S][3][nspec] on the plan's Gaussian grid (SH synthesis
+and the vector transform, both in the library's kernels).
+
+``energy(plan, u)`` returns, per state, the area mean of the linear
+shallow-water energy density, (1/2) (Phibar |V|^2 + Phi^2), integrated with
+the Gauss weights in latitude and the trapezoid rule in longitude.  It is the
+quantity the linear operator conserves (it is skew-Hermitian in the
+energy-scaled variables).  For a state truncated at T on a grid with
+nlat >= T + 1 and nlon > 2 T the quadrature is exact, and the value equals
+(1/4) sum_{n,m} c_m [Phibar a^2 / (n(n+1)) (|zeta|^2 + |delta|^2) + |Phi|^2],
+c_0 = 1, c_m = 2.  The final weighted sums are torch reductions on the GPU.
+"""
+import numpy as np
+
+from . import rexi
+
+
+def _gauss_weights(nlat, device):
+    import torch
+    _, w = np.polynomial.legendre.leggauss(nlat)  # symmetric about the equator
+    return torch.from_numpy(np.ascontiguousarray(w)).to(device)
+
+
+def grid_fields(plan: rexi.Plan, u):
+    """(Phi [S][nlat][nlon], winds [S][2][nlat][nlon]) of states u [S][3][nspec]."""
+    phi = plan.sh_inverse(u[:, 0].contiguous())
+    winds = plan.vortdiv_to_uv(u)
+    return phi, winds
+
+
+def energy(plan: rexi.Plan, u):
+    """Area-mean energy (1/2) <Phibar |V|^2 + Phi^2> of each state (m^4 s^-4)."""
+    p = plan.params
+    phibar = p.gravity * p.mean_depth
+    phi, winds = grid_fields(plan, u)
+    dens = 0.5 * (phibar * (winds * winds).sum(1) + phi * phi)  # [S][nlat][nlon]
+    w = _gauss_weights(p.nlat, u.device)
+    # (1/4 pi) int f dOmega = sum_j w_j (1/nlon) sum_k f_jk / 2
+    return (dens.sum(-1) * w).sum(-1) / (2.0 * p.nlon)
