@@ -367,6 +367,15 @@ def main():
         rec["dispersion"] = dispersion_run(rexi, synth, torch, dev)
     rec["graph_replay_median"] = graph_replay_medians(plan, u)
     rec["vector_transforms"] = vector_run(plan, u, T, w.nlat, torch)
+    # physical check of the timed run: the linear operator conserves the
+    # energy, so 16 REXI steps may change it by the REXI error only (the
+    # spectral sum: the 512 x 256 grid is not exact for the top degree)
+    from paper_1812_03431_amd import diagnostics
+    e0 = diagnostics.spectral_energy(plan, u)
+    e1 = diagnostics.spectral_energy(plan, plan.step(u, w.steps))
+    rec["energy_drift"] = {"steps": w.steps, "max_rel_change": float((e1 / e0 - 1).abs().max().item()),
+                           "quantity": "(1/4) sum c_m [Phibar a^2/(n(n+1)) (|zeta|^2+|delta|^2) + |Phi|^2] "
+                                       "of the 4 benchmark states"}
     if not args.no_cpu_baseline:
         us = torch.from_numpy(synth.random_state(T, S, 0)).to(dev)
         gf = plan.step(us).cpu().numpy()

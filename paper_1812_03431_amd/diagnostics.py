@@ -12,6 +12,11 @@ energy-scaled variables).  For a state truncated at T on a grid with
 nlat >= T + 1 and nlon > 2 T the quadrature is exact, and the value equals
 (1/4) sum_{n,m} c_m [Phibar a^2 / (n(n+1)) (|zeta|^2 + |delta|^2) + |Phi|^2],
 c_0 = 1, c_m = 2.  The final weighted sums are torch reductions on the GPU.
+
+``spectral_energy(plan, u)`` is that sum itself, exact at any grid size; on a
+grid with nlat < T + 1 (such as 512 x 256 at T256) the grid quadrature is not
+exact for the top degrees, and ``energy`` then carries a bias for states with
+much energy there.
 """
 import numpy as np
 
@@ -22,6 +27,22 @@ def _gauss_weights(nlat, device):
     import torch
     _, w = np.polynomial.legendre.leggauss(nlat)  # symmetric about the equator
     return torch.from_numpy(np.ascontiguousarray(w)).to(device)
+
+
+def spectral_energy(plan: rexi.Plan, u):
+    """(1/4) sum c_m [Phibar a^2/(n(n+1)) (|zeta|^2 + |delta|^2) + |Phi|^2] of
+    each state u [S][3][nspec] (the same quantity as ``energy``, exactly)."""
+    import torch
+    p = plan.params
+    phibar = p.gravity * p.mean_depth
+    T = p.T
+    n = np.concatenate([np.arange(m, T + 1) for m in range(T + 1)]).astype(float)
+    cm = np.concatenate([np.full(T + 1 - m, 1.0 if m == 0 else 2.0) for m in range(T + 1)])
+    s2 = np.where(n > 0, phibar * p.radius ** 2 / np.maximum(n * (n + 1), 1.0), 0.0)
+    cm_t = torch.from_numpy(cm).to(u.device)
+    s2_t = torch.from_numpy(s2).to(u.device)
+    a2 = (u.real ** 2 + u.imag ** 2)  # [S][3][nspec]
+    return 0.25 * ((a2[:, 0] + s2_t * (a2[:, 1] + a2[:, 2])) * cm_t).sum(-1)
 
 
 def grid_fields(plan: rexi.Plan, u):

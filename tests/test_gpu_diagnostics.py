@@ -34,6 +34,7 @@ def test_energy_matches_spectral_value_and_is_kept_by_the_step():
     e0 = diagnostics.energy(plan, ut).cpu().numpy()
     want = _spectral_energy(u0, T)
     assert np.max(np.abs(e0 - want) / want) < 1e-12
+    assert np.max(np.abs(diagnostics.spectral_energy(plan, ut).cpu().numpy() - want) / want) < 1e-14
     # the linear operator conserves it; one REXI step changes it by its error only
     e1 = diagnostics.energy(plan, plan.step(ut)).cpu().numpy()
     assert np.max(np.abs(e1 / e0 - 1)) < 1e-10
