@@ -13,7 +13,8 @@ The metric is (pole, m)-block solves per second over the timed region:
 
 Also reported: live HIP-event timing of the fused solve kernel (roofline
 against the FP64 vector peak), the FP64-MFMA Legendre kernels, the plain
-per-term launch form for comparison, the wall-clock of the Gaussian-bump
+per-term launch form for comparison, the vector transforms, the energy drift
+of the benchmark states over the 16 steps, the wall-clock of the Gaussian-bump
 workload over 1.5 days (Section 6.2), the f-sphere dispersion errors of the
 step (Section 6.3), and the CPU oracle timed on a bounded sample of the same
 workload.
