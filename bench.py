@@ -232,8 +232,8 @@ def main():
                     help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
-              f"MI355X; the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs the whole "
+              f"step on a single MI355X (sharding by zonal order is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
