@@ -69,13 +69,31 @@ __device__ void fft_lds(double2* X, const double2* tw, int bits, int nb, bool in
 // F = (1/nlon) DFT, c = 2b + {0: re, 1: im}, s_j = rs[j] (rs may be NULL; it
 // is symmetric about the equator).  These are the B operands of the forward
 // Legendre contraction.  Workgroup g H + j takes field group g.
+// Block b of a launch over G field groups x H row pairs -> (g, j). Blocks are
+// dispatched to the eight XCDs in turn (b mod 8), so when H is a multiple of 8
+// all G groups of row pair j get consecutive blocks of XCD j mod 8: the groups
+// read (inverse) or write (forward) disjoint 16-byte pieces of the same
+// spectral-side lines, which then meet in that XCD's L2 instead of being
+// fetched or written back once per group. Otherwise the plain g-major split.
+__device__ inline void fft_block(int b, int G, int H, int& g, int& j) {
+    if ((H & 7) == 0) {
+        const int i = b >> 3, q = i / G;
+        g = i - q * G;
+        j = q * 8 + (b & 7);
+    } else {
+        g = b / H;
+        j = b - g * H;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ grid, double* __restrict__ EO,
                                                      const double2* __restrict__ tw, const double* __restrict__ wts,
                                                      const double* __restrict__ rs, int nlat, int nlon, int bits,
                                                      int T, int C, int nb) {
     extern __shared__ double2 X[];  // [nb][nlon] data, then [nlon/2] twiddles
     const int H = nlat >> 1, nf = C >> 1;
-    const int g = blockIdx.x / H, j = blockIdx.x - g * H;
+    int g, j;
+    fft_block(blockIdx.x, (nf + nb - 1) / nb, H, g, j);
     const int b0 = g * nb, nbr = min(nb, nf - b0);
     double2* tws = X + nb * nlon;
     for (int k = threadIdx.x; k < nlon / 2; k += blockDim.x) tws[k] = tw[k];
@@ -128,7 +146,9 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
                                                      int T, int C, int nb) {
     extern __shared__ double2 X[];  // [nb][nlon] data, then [nlon/2] twiddles
     const int H = nlat >> 1, nf = C >> 1;
-    const int g = blockIdx.x / H, j = blockIdx.x - g * H, j2 = nlat - 1 - j;
+    int g, j;
+    fft_block(blockIdx.x, (nf + nb - 1) / nb, H, g, j);
+    const int j2 = nlat - 1 - j;
     const int b0 = g * nb, nbr = min(nb, nf - b0);
     double2* tws = X + nb * nlon;
     for (int k = threadIdx.x; k < nb * nlon; k += blockDim.x) X[k] = make_double2(0.0, 0.0);
