@@ -406,6 +406,7 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
                                                           int c_off, int C) {
     extern __shared__ double lds[];
     const LegWork wk = work[blockIdx.x];
+    if (wk.m < 0) return;  // padding slot of the XCD-ordered list
     const int m = wk.m;
     const int Ls = min(kInvSeg, T + 1 - m - wk.n0);  // degrees of this segment
     const int nr = (Ls + kInvRun - 1) / kInvRun;       // restarts of this segment
@@ -585,9 +586,10 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
     // first: all runs of an order share one XCD and its L2, where the order's
     // Fourier block is read from HBM once.  Queues that run out early are
     // padded with empty slots (m = -1).
-    // inverse: four latitude tiles (one per wave) of one order.  One order
-    // per workgroup: pairing m with T - m evens the work per wave but halves
-    // the waves in flight, which measured slower (30 vs 26 us at T256)
+    // inverse: four latitude tiles (one per wave) of one degree segment of one
+    // order.  One order per workgroup: pairing m with T - m evens the work per
+    // wave but halves the waves in flight, which measured slower (30 vs 26 us
+    // at T256)
     constexpr int kXcd = 8;
     std::vector<std::vector<LegRun>> q(kXcd);
     for (int m = 0; m <= T; ++m) {
@@ -605,17 +607,30 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
     std::vector<LegWork> ti;
     const int nl = (H + 15) / 16;
     // inverse: degree segments of kInvSeg, partial slot seg[m] + s; full
-    // segments first (the longest work), each with its latitude tile groups
+    // segments first (the longest work), each with its latitude tile groups.
+    // All tile groups of a segment stage the same spectral block, so they go
+    // to one XCD: the k-th segment in this order to the queue of XCD k % 8,
+    // and the queues are interleaved like the forward list (padding m = -1).
+    // Spread over the XCDs, each group read the block from HBM again (9x the
+    // spectral bytes at T1023 on 1024 latitudes).
     std::vector<int> seg(T + 2, 0);
     for (int m = 0; m <= T; ++m) seg[m + 1] = seg[m] + (Tt - m) / kInvSeg + 1;
+    std::vector<std::vector<LegWork>> qi(kXcd);
+    int kseg = 0;
     for (int full = 1; full >= 0; --full)
         for (int m = 0; m <= T; ++m)
             for (int n0 = 0; m + n0 <= Tt; n0 += kInvSeg) {
                 if ((m + n0 + kInvSeg - 1 <= Tt) != (full == 1)) continue;
+                std::vector<LegWork>& dst = qi[kseg++ % kXcd];
                 for (int t0 = 0; t0 < nl; t0 += 4)
-                    ti.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m] + n0 / kRun, n0,
-                                         seg[m] + n0 / kInvSeg});
+                    dst.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m] + n0 / kRun, n0,
+                                          seg[m] + n0 / kInvSeg});
             }
+    size_t qimax = 0;
+    for (auto& v : qi) qimax = std::max(qimax, v.size());
+    for (size_t k = 0; k < qimax; ++k)
+        for (int x = 0; x < kXcd; ++x) ti.push_back(k < qi[x].size() ? qi[x][k] : LegWork{-1, 0, 0, 0, 0, 0});
+    while (!ti.empty() && ti.back().m < 0) ti.pop_back();
     t.nslots = seg[T + 1];
     t.T = Tt;
     int rc = device_alloc((void**)&t.d_restart, restart.size() * sizeof(double));
