@@ -31,24 +31,56 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
-// In-place radix-2 decimation-in-time FFTs of nb arrays X + f n, f < nb, in
-// LDS (input already in bit-reversed order), one stage at a time over all of
-// them; n = 2^bits.  tw[k] = exp(-2 pi i k / n), k < n/2; conj for the
-// inverse direction.
+__device__ __forceinline__ double2 cmul(double2 w, double2 v) {
+    return make_double2(fma(w.x, v.x, -w.y * v.y), fma(w.x, v.y, w.y * v.x));
+}
+
+__device__ __forceinline__ double2 twiddle(const double2* tw, int k, bool inverse) {
+    double2 w = tw[k];
+    if (inverse) w.y = -w.y;
+    return w;
+}
+
+// In-place decimation-in-time FFTs of nb arrays X + f n, f < nb, in LDS (input
+// already in bit-reversed order); n = 2^bits.  tw[k] = exp(-2 pi i k / n),
+// k < n/2; conj for the inverse direction.  Two radix-2 stages at a time: the
+// butterflies of half-lengths h and 2h over the four elements pos + {0, h, 2h,
+// 3h} of a block of 4h are one radix-4 step with the same arithmetic and
+// twiddles, so a stage pair needs one barrier instead of two.  An odd number of
+// stages starts with one radix-2 stage.  The FFTs are bound by the latency of
+// their barrier-separated stages (11 -> 6 barriers at n = 2048).
 __device__ void fft_lds(double2* X, const double2* tw, int bits, int nb, bool inverse) {
     const int n = 1 << bits, hb = bits - 1;
-    for (int lh = 0; lh < bits; ++lh) {  // butterfly half-length 2^lh
-        const int half = 1 << lh;
+    int lh = 0;  // half-length 2^lh of the next radix-2 stage
+    if (bits & 1) {
+        const double2 w = twiddle(tw, 0, inverse);
         for (int t = threadIdx.x; t < (nb << hb); t += blockDim.x) {
-            const int f = t >> hb, tt = t & ((1 << hb) - 1);
-            const int grp = tt >> lh, pos = tt & (half - 1);
-            const int i = f * n + (grp << (lh + 1)) + pos, j = i + half;
-            double2 w = tw[pos << (hb - lh)];
-            if (inverse) w.y = -w.y;
-            const double2 u = X[i], v0 = X[j];
-            const double2 v = make_double2(fma(w.x, v0.x, -w.y * v0.y), fma(w.x, v0.y, w.y * v0.x));
+            const int i = 2 * t, j = i + 1;
+            const double2 u = X[i], v = cmul(w, X[j]);
             X[i] = make_double2(u.x + v.x, u.y + v.y);
             X[j] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+        lh = 1;
+    }
+    for (; lh + 2 <= bits; lh += 2) {
+        const int h = 1 << lh, q = hb - 1;  // n/4 = 2^q radix-4 steps per array
+        for (int t = threadIdx.x; t < (nb << q); t += blockDim.x) {
+            const int f = t >> q, tt = t & ((1 << q) - 1);
+            const int grp = tt >> lh, pos = tt & (h - 1);
+            const int i0 = f * n + (grp << (lh + 2)) + pos, i1 = i0 + h, i2 = i1 + h, i3 = i2 + h;
+            const double2 w1 = twiddle(tw, pos << (hb - lh), inverse);
+            const double2 w2 = twiddle(tw, pos << (q - lh), inverse);
+            const double2 w3 = twiddle(tw, (pos + h) << (q - lh), inverse);
+            const double2 a0 = X[i0], a2 = X[i2];
+            const double2 t1 = cmul(w1, X[i1]), t3 = cmul(w1, X[i3]);
+            const double2 c0 = make_double2(a0.x + t1.x, a0.y + t1.y), c1 = make_double2(a0.x - t1.x, a0.y - t1.y);
+            const double2 c2 = make_double2(a2.x + t3.x, a2.y + t3.y), c3 = make_double2(a2.x - t3.x, a2.y - t3.y);
+            const double2 u = cmul(w2, c2), v = cmul(w3, c3);
+            X[i0] = make_double2(c0.x + u.x, c0.y + u.y);
+            X[i2] = make_double2(c0.x - u.x, c0.y - u.y);
+            X[i1] = make_double2(c1.x + v.x, c1.y + v.y);
+            X[i3] = make_double2(c1.x - v.x, c1.y - v.y);
         }
         __syncthreads();
     }
