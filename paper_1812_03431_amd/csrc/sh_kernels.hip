@@ -31,6 +31,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
+// Plane strides of the Fourier workspace, in doubles: an EO plane [j][c] of one
+// (order, parity) and a partial slot [row][c] are padded by kFourPad so that
+// the lines of consecutive planes are not a power of two apart.
+constexpr int kFourPad = 32;
+__host__ __device__ __forceinline__ long long eo_plane(int H, int C) { return (long long)H * C + kFourPad; }
+__host__ __device__ __forceinline__ long long slot_plane(int nlat, int C) { return (long long)nlat * C + kFourPad; }
+
 __device__ __forceinline__ double2 cmul(double2 w, double2 v) {
     return make_double2(fma(w.x, v.x, -w.y * v.y), fma(w.x, v.y, w.y * v.x));
 }
@@ -153,8 +160,8 @@ __global__ void __launch_bounds__(256) k_fft_forward(const double* __restrict__ 
     fft_lds(X, tws, bits, nbr, false);
     const double sc = 0.5 * wts[j] * (rs ? rs[j] : 1.0) / nlon;
     for (int m = threadIdx.x; m <= T; m += blockDim.x) {
-        double* e = EO + (((long long)m * 2) * H + j) * C + 2 * b0;
-        double* o = e + (long long)H * C;
+        double* e = EO + (long long)(m * 2) * eo_plane(H, C) + (long long)j * C + 2 * b0;
+        double* o = e + eo_plane(H, C);
         for (int f = 0; f < nbr; ++f) {
             const double2 z = X[f * nlon + m], w = X[f * nlon + (nlon - m) % nlon];
             // 2 X_m = z + conj(w), 2 Y_m = -i (z - conj(w))
@@ -197,8 +204,8 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
             double2 v = make_double2(0.0, 0.0), w = v;
             if (m <= T) {
                 for (int sl = seg[m]; sl < seg[m + 1]; ++sl) {
-                    const double* p = Fw + ((long long)sl * nlat + j) * C + cb;
-                    const double* q = Fw + ((long long)sl * nlat + j2) * C + cb;
+                    const double* p = Fw + sl * slot_plane(nlat, C) + (long long)j * C + cb;
+                    const double* q = Fw + sl * slot_plane(nlat, C) + (long long)j2 * C + cb;
                     v.x += p[0];
                     v.y += p[1];
                     w.x += q[0];
@@ -313,7 +320,7 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
     const bool cok = col < C;
     const long long so = spec_offset(T, m);
     const long long ns = nspec_of(T);
-    const double* Bsrc = EO + ((long long)(m * 2 + r) * H) * Cs + c_off + min(col, C - 1);
+    const double* Bsrc = EO + (long long)(m * 2 + r) * eo_plane(H, Cs) + c_off + min(col, C - 1);
     const int nblk = (H + kFwdLat - 1) / kFwdLat;
     const int nit = rn.nrun * nblk;  // (run, latitude block) iterations
     const bool gen = tid < kFwdLat;
@@ -504,9 +511,9 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
             if (jj < H) {
                 // streaming stores: the partials go out while the kernel runs
                 // instead of as dirty L2 lines written back at its end
-                __builtin_nontemporal_store(ae[q] + ao[q], Fw + ((long long)wk.slot * nlat + jj) * Cs + c_off + col);
+                __builtin_nontemporal_store(ae[q] + ao[q], Fw + wk.slot * slot_plane(nlat, Cs) + (long long)jj * Cs + c_off + col);
                 __builtin_nontemporal_store(ae[q] - ao[q],
-                                            Fw + ((long long)wk.slot * nlat + (nlat - 1 - jj)) * Cs + c_off + col);
+                                            Fw + wk.slot * slot_plane(nlat, Cs) + (long long)(nlat - 1 - jj) * Cs + c_off + col);
             }
         }
     }
@@ -788,7 +795,8 @@ int sh_setup(rexi_plan* pl) {
     // Fourier workspace: the forward's even/odd parts of T + 1 orders, or the
     // inverse's partial slots
     const size_t nsl = std::max<size_t>(T + 1, std::max(pl->leg.nslots, pl->legv.nslots));
-    if (!rc) rc = device_alloc((void**)&pl->d_four, nsl * nlat * 2 * pl->prm.max_fields * sizeof(double));
+    // (T + 1) x 2 EO planes or nslots slots, each padded by kFourPad
+    if (!rc) rc = device_alloc((void**)&pl->d_four, nsl * (nlat * 2 * pl->prm.max_fields + 2 * kFourPad) * sizeof(double));
     if (!rc && pl->prm.max_fields >= 2)
         rc = device_alloc((void**)&pl->d_vspec, (size_t)pl->prm.max_fields * nspec_of(T + 1) * sizeof(double2));
     if (rc) return rc;
