@@ -158,7 +158,7 @@ struct rexi_plan {
     double* d_mu = nullptr;       // northern Gauss nodes [nhalf]
     double* d_wts = nullptr;      // Gauss weights
     double* d_rcos = nullptr;     // 1 / cos(lat_j) [nlat]
-    double* d_four = nullptr;     // Fourier workspace [slots][nlat][2B] (slots >= T+1)
+    double* d_four = nullptr;     // Fourier workspace [slots][nlat][2B] + padding per plane (slots >= T+1)
     double2* d_twiddle = nullptr; // FFT twiddles
     double2* d_vspec = nullptr;   // vector transforms: [max_fields][nspec(T+1)]
 

@@ -5,7 +5,8 @@
 // (the m = 0 term uses Re(xi_n^0)).
 //
 // Longitude: one workgroup per pair of grid rows j, j' = nlat-1-j runs one
-// radix-2 complex FFT of length nlon in LDS for both rows.  Latitude: per
+// complex FFT of length nlon (radix-2 stages taken in pairs) in LDS for both
+// rows.  Latitude: per
 // zonal order m the Legendre sum is a small dense contraction (T+1-m degrees
 // x nlat/2 latitudes x 2B real columns) and runs on FP64 MFMA
 // (v_mfma_f64_16x16x4f64).  Gauss latitudes are symmetric about the equator
@@ -16,6 +17,7 @@
 // Fourier workspace (c = 2b + {0: re, 1: im}): the analysis writes the
 // weighted even/odd parts EO[m][0|1][j][c], j < nlat/2; the synthesis writes
 // partial sums Fw[slot][j][c] of degree segments, which the inverse FFT adds.
+// Each (m, parity) plane and each slot is padded by kFourPad doubles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
