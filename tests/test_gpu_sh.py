@@ -81,6 +81,28 @@ def test_round_trip_at_the_largest_grid():
     assert err < 1e-11, err
 
 
+def test_round_trip_many_fields_at_t1023():
+    # T1023 on 2048 x 1024 with 16 fields (32 real columns): the workspace
+    # planes are a power of two apart before padding, 512 row pairs fill the
+    # XCD-ordered FFT blocks, and every order has up to 8 partial slots
+    import torch
+    import paper_1812_03431_amd as rexi
+    dev = torch.device("cuda:0")
+    T, nlat, nlon, B = 1023, 1024, 2048, 16
+    w = synth.Workload("big", T=T, nlat=nlat, nlon=nlon, dt=3600.0, M=8, states=1)
+    plan = rexi.plan_for(w, max_fields=B)
+    u = torch.from_numpy(synth.random_state(T, 6, 11).reshape(18, -1)[:B].copy()).to(dev)
+    g = plan.sh_inverse(u)
+    back = plan.sh_forward(g)
+    err = ((back - u).abs().amax(1) / u.abs().amax(1)).max().item()
+    assert err < 1e-11, err
+    # a second call of the same plan with fewer fields (one column tile)
+    u3 = u[:3].contiguous()
+    back3 = plan.sh_forward(plan.sh_inverse(u3))
+    err3 = ((back3 - u3).abs().amax(1) / u3.abs().amax(1)).max().item()
+    assert err3 < 1e-11, err3
+
+
 def _random_shapes(n, seed=2024):
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
