@@ -66,8 +66,11 @@ typedef struct rexi_plan rexi_plan;
 
 /* Parameters of a plan.
  *   T                 truncation (1 <= T <= 1023)
- *   nlat, nlon        Gaussian grid of the transforms (nlat >= 2, nlon a power of
- *                     two, 4 <= nlon <= 4096, T < nlon); 0, 0 = no transforms
+ *   nlat, nlon        Gaussian grid of the transforms: nlat even, 2 <= nlat <= 2048
+ *                     (the transforms pair latitude j with nlat-1-j); nlon a power
+ *                     of two, 4 <= nlon <= 4096, T < nlon; 0, 0 = no transforms.
+ *                     Outside these ranges rexi_plan_create returns REXI_EINVAL
+ *                     before it allocates anything.
  *   radius, omega, gravity, mean_depth
  *                     planet radius a (m), rotation rate Omega (1/s), g (m/s^2),
  *                     mean depth H (m); Phibar = g H (Eq. (1), Section 6)
@@ -205,6 +208,28 @@ int rexi_plan_autotune(rexi_plan *plan, int S, void *stream, int *chosen);
  * S states; REXI_EINVAL if out of range.  *count (may be NULL) receives the
  * number of candidates. */
 int rexi_plan_set_schedule(rexi_plan *plan, int S, int index, int *count);
+
+/* *index receives the schedule candidate that steps with S states use now
+ * (the default until rexi_plan_autotune or rexi_plan_set_schedule). */
+int rexi_plan_get_schedule(rexi_plan *plan, int S, int *index);
+
+/* Compiled variants of the fused solve kernel (the batched step, or with
+ * per_term = 1 the per-term form): variant i tiles a chain with se[i]
+ * elements per lane, moves values between the lanes of a chain with
+ * kind[i] (0 ds_bpermute, 1 DPP within 16-lane rows, 2 DPP and
+ * permlane16_swap over row pairs) and solves states_per_item[i] states per
+ * work item, sharing each pole's factorisation among them.  Host only.
+ *   capacity  entries the three arrays can hold (0 = only *count)
+ *   se, kind, states_per_item  host int arrays or NULL
+ *   count     receives the number of variants (may exceed capacity) */
+int rexi_solve_variants(int per_term, int capacity, int *se, int *kind, int *states_per_item, int *count);
+
+/* The solve launches of one schedule candidate for S states (index as for
+ * rexi_plan_set_schedule; -1 = the per-term schedule, which the first
+ * rexi_step_per_term call with S builds): per launch the variant's (se,
+ * kind, states_per_item), as rexi_solve_variants reports them. */
+int rexi_plan_schedule_classes(rexi_plan *plan, int S, int index, int capacity, int *se, int *kind,
+                               int *states_per_item, int *count);
 
 /* Step graphs.  By default every step is replayed as a captured HIP graph
  * (solve launches + reduction), built on first use per (S, direction, buffer)

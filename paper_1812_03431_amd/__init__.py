@@ -5,8 +5,7 @@ The arithmetic lives in the HIP library ``librexi.so`` (C ABI in
 entry points, using torch tensors for device memory and streams.
 """
 from .rexi import (Plan, RexiError, RexiParams, Step, library_path, load_library, params_for, plan_for,
-                   rexi_coeffs,
-                   run)
+                   rexi_coeffs, run, solve_variants)
 
 __all__ = ["Plan", "RexiError", "RexiParams", "Step", "library_path", "load_library", "params_for", "plan_for",
-           "rexi_coeffs", "run"]
+           "rexi_coeffs", "run", "solve_variants"]

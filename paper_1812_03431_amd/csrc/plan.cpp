@@ -17,6 +17,7 @@ namespace rexi {
 
 bool solve_variant_supported(int SE, int kind, bool per_term);
 int solve_waves_per_item();
+int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap);
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
                         hipStream_t s);
 hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int adjoint, hipStream_t s);
@@ -102,7 +103,8 @@ int check_params(const rexi_params* p) {
     if (p->fsphere != 0 && p->fsphere != 1) return fail(REXI_EINVAL, "fsphere must be 0 or 1");
     if (p->fsphere && !std::isfinite(p->f0)) return fail(REXI_EINVAL, "f0 must be finite");
     if (p->nlat != 0 || p->nlon != 0) {
-        if (p->nlat < 2 || p->nlat > 4096) return fail(REXI_EINVAL, "nlat must be in [2, 4096]");
+        if (p->nlat < 2 || p->nlat > 2048 || (p->nlat & 1))
+            return fail(REXI_EINVAL, "nlat must be even and in [2, 2048]");
         if (p->nlon < 4 || p->nlon > 4096 || (p->nlon & (p->nlon - 1)))
             return fail(REXI_EINVAL, "nlon must be a power of two in [4, 4096]");
         if (p->T >= p->nlon) return fail(REXI_EINVAL, "T must be below nlon");
@@ -753,6 +755,17 @@ int rexi_plan_set_schedule(rexi_plan* plan, int S, int index, int* count) {
     return REXI_OK;
 }
 
+int rexi_plan_get_schedule(rexi_plan* plan, int S, int* index) {
+    if (!plan || !index) return fail(REXI_EINVAL, "NULL argument");
+    if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "f-sphere plans have no schedules");
+    if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
+    std::vector<Schedule>* c = nullptr;
+    int rc = schedules_for(plan, S, &c);
+    if (rc) return rc;
+    *index = plan->chosen[S];
+    return REXI_OK;
+}
+
 int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
     if (!plan) return fail(REXI_EINVAL, "plan is NULL");
     if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "f-sphere plans have no schedules");
@@ -799,6 +812,41 @@ int rexi_plan_autotune(rexi_plan* plan, int S, void* stream, int* chosen) {
     if (plan->chosen[S] != best) drop_graphs(plan);
     plan->chosen[S] = best;
     if (chosen) *chosen = best;
+    return REXI_OK;
+}
+
+int rexi_solve_variants(int per_term, int capacity, int* se, int* kind, int* states_per_item, int* count) {
+    if (capacity < 0) return fail(REXI_EINVAL, "capacity must be >= 0");
+    const int n = solve_variant_list(per_term != 0, se, kind, states_per_item, capacity);
+    if (count) *count = n;
+    return REXI_OK;
+}
+
+int rexi_plan_schedule_classes(rexi_plan* plan, int S, int index, int capacity, int* se, int* kind,
+                               int* states_per_item, int* count) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "f-sphere plans have no schedules");
+    if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
+    if (capacity < 0) return fail(REXI_EINVAL, "capacity must be >= 0");
+    const Schedule* sc = nullptr;
+    if (index == -1) {
+        if ((int)plan->per_term.size() <= S || plan->per_term[S].items.empty())
+            return fail(REXI_EINVAL, "the per-term schedule for S is built by the first rexi_step_per_term call");
+        sc = &plan->per_term[S];
+    } else {
+        std::vector<Schedule>* c = nullptr;
+        int rc = schedules_for(plan, S, &c);
+        if (rc) return rc;
+        if (index < -1 || index >= (int)c->size()) return fail(REXI_EINVAL, "schedule index out of range");
+        sc = &(*c)[index];
+    }
+    const int n = (int)sc->launches.size();
+    for (int i = 0; i < n && i < capacity; ++i) {
+        if (se) se[i] = sc->launches[i].SE;
+        if (kind) kind[i] = sc->launches[i].kind;
+        if (states_per_item) states_per_item[i] = sc->ST;
+    }
+    if (count) *count = n;
     return REXI_OK;
 }
 

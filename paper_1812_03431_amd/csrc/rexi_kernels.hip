@@ -832,6 +832,24 @@ bool solve_variant_supported(int SE, int kind, bool per_term) {
 }
 int solve_waves_per_item() { return kWaves; }
 
+int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap) {
+    int n = 0;
+    auto put = [&](int a, int b) {
+        if (n < cap) {
+            if (se) se[n] = a;
+            if (kind) kind[n] = b;
+            if (st) st[n] = 1;
+        }
+        ++n;
+    };
+    if (per_term) {
+        for (const auto& v : kPerTermVariants) put(v[0], v[1]);
+    } else {
+        for (const auto& v : kVariants) put(v[0], v[1]);
+    }
+    return n;
+}
+
 // Internal launchers used by the C ABI (plan.cpp).
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
                         hipStream_t s) {

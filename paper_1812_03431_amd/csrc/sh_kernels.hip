@@ -767,9 +767,8 @@ int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hi
 
 int sh_setup(rexi_plan* pl) {
     const int T = pl->T, nlat = pl->prm.nlat, nlon = pl->prm.nlon;
-    if (nlat % 2) return fail(REXI_EUNSUPPORTED, "nlat must be even");
-    if (nlat > 2048) return fail(REXI_EUNSUPPORTED, "nlat above 2048");
-    if ((long long)nlon * 16 > 64 * 1024) return fail(REXI_EUNSUPPORTED, "nlon above 4096");
+    // the plan's parameter check has already refused these (before allocating)
+    if (nlat % 2 || nlat > 2048 || nlon > 4096) return fail(REXI_EINVAL, "grid outside the supported range");
     pl->nlat = nlat;
     pl->nlon = nlon;
     pl->nhalf = nlat / 2;

@@ -59,6 +59,9 @@ def load_library():
         "rexi_plan_set_graphs": [P, c_int],
         "rexi_plan_set_streams": [P, c_int],
         "rexi_plan_kernel_time": [P, c_int, POINTER(c_double), POINTER(c_longlong)],
+        "rexi_plan_get_schedule": [P, c_int, POINTER(c_int)],
+        "rexi_solve_variants": [c_int, c_int, P, P, P, POINTER(c_int)],
+        "rexi_plan_schedule_classes": [P, c_int, c_int, c_int, P, P, P, POINTER(c_int)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -85,6 +88,22 @@ def rexi_coeffs(M: int, h: float, L: int = 11, normalize: bool = True):
     _check(lib.rexi_coeffs(M, h, L, int(normalize), n.value, *(o.ctypes.data for o in out), byref(n)),
            "rexi_coeffs")
     return tuple(out)
+
+
+def _int_triples(call, what):
+    """Run a (capacity, se, kind, st, count) query twice: size, then fill."""
+    n = c_int(0)
+    _check(call(0, None, None, None, byref(n)), what)
+    arrs = [np.zeros(max(1, n.value), dtype=np.int32) for _ in range(3)]
+    _check(call(n.value, *(a.ctypes.data for a in arrs), byref(n)), what)
+    return [tuple(int(a[i]) for a in arrs) for i in range(n.value)]
+
+
+def solve_variants(per_term: bool = False):
+    """Compiled solve variants as (elements per lane, move kind, states per item)."""
+    lib = load_library()
+    return _int_triples(lambda cap, a, b, c, n: lib.rexi_solve_variants(int(per_term), cap, a, b, c, n),
+                        "rexi_solve_variants")
 
 
 def params_for(w, max_states=None, max_fields=None, normalize=True, dt=None, grid=True, fsphere=None) -> RexiParams:
@@ -247,6 +266,18 @@ class Plan:
         n = c_int(0)
         _check(self._lib.rexi_plan_set_schedule(self._h, S, -1, byref(n)), "rexi_plan_set_schedule")
         return n.value
+
+    def chosen_schedule(self, S: int) -> int:
+        """Index of the schedule candidate that steps with S states use now."""
+        i = c_int(-1)
+        _check(self._lib.rexi_plan_get_schedule(self._h, S, byref(i)), "rexi_plan_get_schedule")
+        return i.value
+
+    def schedule_classes(self, S: int, index: int):
+        """(elements per lane, move kind, states per item) of each solve launch
+        of schedule ``index`` (-1: the per-term schedule)."""
+        return _int_triples(lambda cap, a, b, c, n: self._lib.rexi_plan_schedule_classes(
+            self._h, S, index, cap, a, b, c, n), "rexi_plan_schedule_classes")
 
     def set_schedule(self, S: int, index: int):
         _check(self._lib.rexi_plan_set_schedule(self._h, S, index, None), "rexi_plan_set_schedule")

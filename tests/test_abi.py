@@ -75,5 +75,27 @@ def test_plan_argument_errors(lib):
     bad = rexi.RexiParams.from_buffer_copy(p)
     bad.dt = -1.0
     assert lib.rexi_plan_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    # the transforms pair latitude rows j and nlat-1-j and hold at most 2048
+    # rows: odd or larger nlat is refused by the parameter check, before any
+    # device allocation (so it is refused here, without a GPU, as well)
+    for nlat in (3, 65, 2050, 4096):
+        bad = rexi.RexiParams.from_buffer_copy(p)
+        bad.nlat = nlat
+        assert lib.rexi_plan_create(ctypes.byref(bad), ctypes.byref(h)) == -1, nlat
+        assert b"nlat" in lib.rexi_last_error()
+        assert not h.value
     assert lib.rexi_plan_destroy(None) == -1
     assert lib.rexi_step(None, None, None, 1, 1, None) == -1
+
+
+def test_solve_variant_query():
+    # host-only query of the compiled solve variants: the per-term form's are
+    # a subset of the batched form's tilings, and every variant tiles with an
+    # even number of elements per lane and a known move kind
+    import paper_1812_03431_amd as rexi
+    v = rexi.solve_variants()
+    pt = rexi.solve_variants(per_term=True)
+    assert len(v) >= 10 and len(set(v)) == len(v)
+    assert {(se, k) for se, k, _ in pt} <= {(se, k) for se, k, _ in v}
+    for se, kind, st in v + pt:
+        assert se % 2 == 0 and 2 <= se <= 16 and kind in (0, 1, 2) and st >= 1

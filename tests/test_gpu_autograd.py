@@ -41,15 +41,23 @@ def test_gradient_matches_central_differences_t128():
     target = synth.random_state(w.T, 1, 100)[:, 0].copy()
     _, g = _grad(plan, u0, target, w.steps, w.checkpoint_every)
     dirs = np.concatenate([synth.random_state(w.T, 1, 200 + i) for i in range(ndir)])
-    eps = 1e-6
-    batch = np.concatenate([u0 + eps * dirs, u0 - eps * dirs])   # [2 ndir][3][nspec]
-    with torch.no_grad():
-        out = plan.step(torch.from_numpy(batch).cuda(), w.steps).cpu().numpy()
-    loss = np.sum(np.abs(out[:, 0] - target) ** 2, axis=1)
-    fd = (loss[:ndir] - loss[ndir:]) / (2 * eps)
     an = np.array([np.real(np.vdot(g[0], d)) for d in dirs])
-    err = np.abs(fd - an) / np.maximum(np.abs(an), 1e-300)
-    assert np.max(err) < 1e-6, err
+    # The loss is quadratic in u0 (the step is linear), so central differences
+    # equal the directional derivative for every eps; what remains is
+    # rounding.  Each loss carries the steps' own rounding, about 1e-13 of the
+    # loss and different for u0 + eps d and u0 - eps d, so the difference
+    # quotient errs by up to about 1e-13 / eps: 1e-7 at the workload's
+    # eps = 1e-6 (measured 2.6e-8; bound 2e-7) and 1e-11 at eps = 1e-2
+    # (measured 1.2e-12; bound 1e-9).
+    for eps, bound in ((1e-6, 2e-7), (1e-2, 1e-9)):
+        batch = np.concatenate([u0 + eps * dirs, u0 - eps * dirs])   # [2 ndir][3][nspec]
+        with torch.no_grad():
+            out = plan.step(torch.from_numpy(batch).cuda(), w.steps).cpu().numpy()
+        loss = np.sum(np.abs(out[:, 0] - target) ** 2, axis=1)
+        fd = (loss[:ndir] - loss[ndir:]) / (2 * eps)
+        err = np.abs(fd - an) / np.maximum(np.abs(an), 1e-300)
+        print(f"  eps {eps:.0e}: max rel error {np.max(err):.2e}", flush=True)
+        assert np.max(err) < bound, (eps, err)
 
 
 def test_gradient_matches_dense_adjoint_t31():

@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle import operator as op, rexi as orexi, sh as osh
-from tests.gpu_common import A, OM, PB, assert_parity, block_mask, oracle_coeffs
+from tests.gpu_common import A, OM, PB, assert_parity, oracle_coeffs
 
 pytestmark = pytest.mark.gpu
 
@@ -42,5 +42,6 @@ def test_bumps_over_one_and_a_half_days(name, orders):
             R = orexi.rexi_propagator(w.T, m, w.dt, co, A, OM, PB)
             blk = np.linalg.matrix_power(R, w.steps) @ op.block_of(v0, w.T, m)
             op.scatter_block(want, blk, w.T, m)
-    mask = block_mask(w.T, orders)
-    assert_parity(got[:, :, mask], want[:, :, mask], what=f"{name} orders {orders}")
+    # the GPU steps its own analysis of the grid, the oracle its own: whole
+    # variables over the sampled orders only (see assert_parity)
+    assert_parity(got, want, w.T, orders, what=f"{name} orders {orders}", blocks=False)

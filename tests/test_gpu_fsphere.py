@@ -30,10 +30,10 @@ def test_fsphere_steps_match_oracle():
     plan = _plan(w, 3, f0)
     got = plan.step(torch.from_numpy(u0).to(dev)).cpu().numpy()
     want = orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, fsphere=f0)
-    assert_parity(got, want, what="f-sphere forward")
+    assert_parity(got, want, w.T, what="f-sphere forward")
     got_a = plan.step_adjoint(torch.from_numpy(u0).to(dev)).cpu().numpy()
     want_a = orexi.rexi_step(u0, w.T, w.dt, co, A, OM, PB, adjoint=True, fsphere=f0)
-    assert_parity(got_a, want_a, what="f-sphere adjoint")
+    assert_parity(got_a, want_a, w.T, what="f-sphere adjoint")
 
 
 def test_fsphere_adjoint_dot_product_and_multistep():
