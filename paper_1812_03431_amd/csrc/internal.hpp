@@ -75,28 +75,32 @@ struct MInfo {
     int slot_base;  // first chain slot of this m (chain p at slot_base + p L)
 };
 
-// One work item of the fused solve: chain p of order m, states
-// [tile*ST, tile*ST + ST), poles [k0, k1).  Its partial sums go to
-// part + part_off (complex units), layout [ST][2][L].
+// One work item of the fused solve: chain p of order m, the R states
+// [tile*R, tile*R + R) (R = the launch's states per item), poles [k0, k1).
+// Its partial sums go to part + part_off (complex units), layout [R][2][L].
 struct Item {
     int m, p, tile, k0, k1;
     long long part_off;
 };
 
-// Per (m, p, tile): where its nr partials start (consecutive items).
+// Per (m, p, state): where the partial sums of that state start in the
+// first of its nr consecutive items, and the states per item st of those
+// items (successive items are st * 2L complex entries apart).
 struct Group {
     long long part_off;
     int nr;
-    int pad;
+    int st;
 };
 
 // One launch of the solve kernel: items [item0, item0 + nitems) share the
-// elements-per-lane class SE and the cross-lane move kind.
+// elements-per-lane class SE, the cross-lane move kind and the number of
+// states per item (rot), whose solves share each pole's factorisation.
 struct Launch {
     int SE;
     int kind;  // cross-lane moves: 0 ds_bpermute, 1 DPP within 16-lane rows, 2 DPP over row pairs
     int item0, nitems;
     int pmax;  // largest lane group of the launch (sizes its LDS)
+    int rot;   // states per work item
 };
 
 constexpr int kMaxLaunches = 8;  // solve launches per step (tile classes)
@@ -104,12 +108,12 @@ constexpr int kMaxLaunches = 8;  // solve launches per step (tile classes)
 struct Schedule {
     bool persistent = false;  // resident grid + atomic work counter per launch
     int SM = 4;       // largest elements-per-lane class used
-    int ST = 1;       // states per work item
+    int rot_max = 1;  // largest states-per-item the schedule may use
     int S = 0;        // states this schedule serves
     std::vector<Launch> launches;
     std::vector<MInfo> minfo;
     std::vector<Item> items;
-    std::vector<Group> groups;  // index ((m * 2 + p) * ntiles + tile)
+    std::vector<Group> groups;  // index ((m * 2 + p) * S + state)
     long long part_size = 0;    // complex entries
     // device copies
     MInfo* d_minfo = nullptr;

@@ -15,7 +15,7 @@
 
 namespace rexi {
 
-bool solve_variant_supported(int SE, int kind, bool per_term);
+bool solve_variant_supported(int SE, int kind, int rot, bool per_term);
 int solve_waves_per_item();
 int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap);
 hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
@@ -182,46 +182,67 @@ void tile_class(int policy, int L, int& SE, int& kind) {
 const char* kPolicyName[] = {"8", "8/16", "16", "8/12/16", "4/8", "fine"};
 constexpr int kPolicies = 6;
 
-// Work split of one candidate schedule.  Items are (m, chain, state, pole
-// range); the number of items per (m, chain, state) follows a cost model per
-// wave iteration (elements x sweep work + log2(P) reduction levels, scaled by
-// the waves a SIMD can hold for the class).  One launch per class; items in a
-// launch run longest first.
-int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, bool per_term, Schedule& out) {
+// Work split of one candidate schedule.  Items are (m, chain, state tile,
+// pole range).  Per order the tile holds R states, the largest of 4, 2, 1
+// that is at most the mode's limit, divides S, fits the chain groups of a wave
+// (P R <= 64) and is compiled; the item's waves then factorise each pole
+// once for its R states.  Modes: 0 one state per item; 1 the most states per
+// item in every class; 2 the same only for tiles of at most 6 or at least 14
+// elements per lane (measured at T256: sharing gains 14-20% there, while
+// the 8-element tile loses its second wave per SIMD to the factorisation's
+// LDS and the 10- and 12-element tiles gain nothing).  The number of items per (m, chain, tile) follows a
+// cost model per wave iteration (elements x sweep work + log2(P) reduction
+// levels, the factorising pass and R - 1 passes that reuse it, scaled by the
+// waves a SIMD can hold for the class).  One launch per (SE, kind, R) class;
+// items in a launch run longest first.
+int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, bool per_term, int rot_mode,
+                   Schedule& out) {
+    const int rot_max = rot_mode == 0 ? 1 : 4;
     const int T = pl->T, N = per_term ? 1 : pl->N;
     out = Schedule();
-    out.ST = 1;
+    out.rot_max = rot_max;
     out.S = S;
     out.minfo = chain_layout(T);
-    struct Unit { int m, p, tile; double cost; int iters; int G; int cls; };
+    struct Unit { int m, p, tile, rot; double cost; int iters; int G; int cls; };
     std::vector<Unit> units;
-    std::vector<std::pair<int, int>> classes;
+    struct Cls { int SE, kind, rot; };
+    std::vector<Cls> classes;
     double total = 0;
     for (int m = 0; m <= T; ++m) {
         MInfo& mi = out.minfo[m];
         int SE, kind;
         tile_class(policy, mi.L, SE, kind);
-        if (!solve_variant_supported(SE, kind, per_term)) return fail(REXI_EUNSUPPORTED, "tile class not compiled");
         int P = 1;
         while (P * SE < mi.L) P *= 2;
         if (kind == 1 ? P > 16 : kind == 2 ? P != 32 : P > 64)
             return fail(REXI_EUNSUPPORTED, "chain length does not fit this tiling");
+        int rot = 1;
+        const bool share = rot_mode == 1 || (rot_mode == 2 && (SE <= 6 || SE >= 14));
+        for (int r : {4, 2})
+            if (share && r <= rot_max && S % r == 0 && P * r <= 64 && solve_variant_supported(SE, kind, r, per_term)) {
+                rot = r;
+                break;
+            }
+        if (!solve_variant_supported(SE, kind, rot, per_term)) return fail(REXI_EUNSUPPORTED, "tile class not compiled");
         mi.P = P;
         mi.s = SE;
         out.SM = std::max(out.SM, SE);
         int cls = -1;
         for (int c = 0; c < (int)classes.size(); ++c)
-            if (classes[c].first == SE && classes[c].second == kind) cls = c;
-        if (cls < 0) { cls = (int)classes.size(); classes.push_back({SE, kind}); }
+            if (classes[c].SE == SE && classes[c].kind == kind && classes[c].rot == rot) cls = c;
+        if (cls < 0) { cls = (int)classes.size(); classes.push_back({SE, kind, rot}); }
         const int G = 64 / P * (per_term ? 1 : solve_waves_per_item());  // poles per workgroup iteration
         int lg = 0;
         while ((1 << lg) < P) ++lg;
-        const double occ = SE <= 8 ? 2.0 : 1.0;
-        const double it_cost = (SE * 100.0 + lg * (kind == 0 ? 160.0 : kind == 2 ? 100.0 : 90.0) + 60.0) / occ;
+        const double occ = (SE <= 8 && rot == 1) ? 2.0 : 1.0;
+        const double lvl = kind == 0 ? 160.0 : kind == 2 ? 100.0 : 90.0;
+        const double fused = SE * 100.0 + lg * lvl + 60.0;
+        const double reuse = SE * 65.0 + lg * 0.5 * lvl + 40.0;
+        const double it_cost = (fused + (rot - 1) * reuse) / occ;
         const int iters = (N + G - 1) / G;
         for (int p = 0; p < 2; ++p)
-            for (int t = 0; t < S; ++t) {
-                units.push_back({m, p, t, it_cost * iters, iters, G, cls});
+            for (int t = 0; t < S / rot; ++t) {
+                units.push_back({m, p, t, rot, it_cost * iters, iters, G, cls});
                 total += it_cost * iters;
             }
     }
@@ -232,10 +253,13 @@ int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, boo
     for (const Unit& u : units) {
         int nr = (int)std::lround(u.cost / target);
         nr = std::max(1, std::min(nr, u.iters));
-        const long long sz = 2LL * out.minfo[u.m].L;
-        Group& gr = out.groups[((size_t)u.m * 2 + u.p) * S + u.tile];
-        gr.part_off = off;
-        gr.nr = nr;
+        const long long L2 = 2LL * out.minfo[u.m].L;
+        for (int q = 0; q < u.rot; ++q) {
+            Group& gr = out.groups[((size_t)u.m * 2 + u.p) * S + u.tile * u.rot + q];
+            gr.part_off = off + q * L2;
+            gr.nr = nr;
+            gr.st = u.rot;
+        }
         for (int r = 0; r < nr; ++r) {
             const int i0 = (int)((long long)u.iters * r / nr), i1 = (int)((long long)u.iters * (r + 1) / nr);
             Item it;
@@ -245,7 +269,7 @@ int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, boo
             it.k0 = i0 * u.G;
             it.k1 = std::min(N, i1 * u.G);
             it.part_off = off;
-            off += sz;
+            off += u.rot * L2;
             by_class[u.cls].push_back({u.cost * (i1 - i0) / u.iters, it});
         }
     }
@@ -256,14 +280,14 @@ int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, boo
         });
         int pmax = 1;
         for (auto& x : v) pmax = std::max(pmax, out.minfo[x.second.m].P);
-        Launch L{classes[c].first, classes[c].second, (int)out.items.size(), (int)v.size(), pmax};
+        Launch L{classes[c].SE, classes[c].kind, (int)out.items.size(), (int)v.size(), pmax, classes[c].rot};
         for (auto& x : v) out.items.push_back(x.second);
         out.launches.push_back(L);
     }
     out.part_size = off;
     char buf[96];
-    std::snprintf(buf, sizeof buf, "%s_items%lld%s", kPolicyName[policy], (long long)out.items.size(),
-                  per_term ? "_perterm" : "");
+    std::snprintf(buf, sizeof buf, "%s_items%lld%s%s", kPolicyName[policy], (long long)out.items.size(),
+                  rot_mode == 1 ? "_shared" : rot_mode == 2 ? "_mixed" : "", per_term ? "_perterm" : "");
     out.name = buf;
     int rc = upload(&out.d_minfo, out.minfo);
     if (!rc) rc = upload(&out.d_items, out.items);
@@ -303,11 +327,21 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
     std::vector<Schedule>& c = pl->sched[S];
     if (c.empty()) {
         const long long tg[] = {2048, 4096, 8192};
+        // states per item (see build_schedule): one (each state factorises
+        // its own poles), and for an even number of states up to four sharing
+        // each factorisation, in every tile class or in some
+        std::vector<int> rots = {0};
+        if (S % 2 == 0) {
+            rots.push_back(1);
+            rots.push_back(2);
+        }
+        int dflt = -1;
+        for (int rot : rots)
         for (int persistent = 0; persistent < 2; ++persistent)
             for (int policy = 0; policy < kPolicies; ++policy)
                 for (long long t : tg) {
                     Schedule sc;
-                    int rc = build_schedule(pl, S, policy, t, false, sc);
+                    int rc = build_schedule(pl, S, policy, t, false, rot, sc);
                     if (rc == REXI_EUNSUPPORTED) { free_schedule(sc); continue; }
                     if (rc) { free_schedule(sc); return rc; }
                     if ((int)sc.launches.size() > kMaxLaunches) { free_schedule(sc); continue; }
@@ -315,10 +349,13 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
                     if (sc.persistent) sc.name = "persistent_" + sc.name;
                     rc = ensure_part(pl, sc.part_size);
                     if (rc) { free_schedule(sc); return rc; }
+                    // until autotuned: "fine", ~4096 items, one launch per item,
+                    // states sharing factorisations where that measured faster
+                    if (!persistent && policy == 5 && t == 4096 && rot == rots.back()) dflt = (int)c.size();
                     c.push_back(sc);
                 }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");
-        pl->chosen[S] = std::min<int>(5 * 3 + 1, (int)c.size() - 1);  // until autotuned: "fine", ~4096 items
+        pl->chosen[S] = dflt >= 0 ? dflt : 0;
     }
     *out = &c;
     return REXI_OK;
@@ -719,7 +756,7 @@ int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* s
         if ((int)plan->per_term.size() <= S) plan->per_term.resize(S + 1);
         Schedule& sc = plan->per_term[S];
         if (sc.items.empty()) {
-            rc = build_schedule(plan, S, 0, 0, true, sc);  // 8 elements per lane, one wave per chain
+            rc = build_schedule(plan, S, 0, 0, true, 0, sc);  // 8 elements per lane, one wave per chain
             if (rc) { free_schedule(sc); sc = Schedule(); return rc; }
         }
         if (sc.part_size > plan->acc_capacity) {
@@ -844,7 +881,7 @@ int rexi_plan_schedule_classes(rexi_plan* plan, int S, int index, int capacity, 
     for (int i = 0; i < n && i < capacity; ++i) {
         if (se) se[i] = sc->launches[i].SE;
         if (kind) kind[i] = sc->launches[i].kind;
-        if (states_per_item) states_per_item[i] = sc->ST;
+        if (states_per_item) states_per_item[i] = sc->launches[i].rot;
     }
     if (count) *count = n;
     return REXI_OK;

@@ -106,7 +106,6 @@ struct SolveArgs {
 };
 
 constexpr int kWaves = 4;   // waves per workgroup; they share one item's staged data
-constexpr int kStage = 8;   // doubles staged per chain position
 
 __device__ __forceinline__ cd crcp_newton(cd a) {
     // 1/(x + i y) = (x - i y)/(x^2 + y^2).  The real reciprocal r of v_rcp_f64
@@ -196,32 +195,74 @@ struct Mover {
     }
 };
 
-// One cyclic-reduction level with stride D: matrix row (A, B, C) and two
-// right-hand sides (Du, Dw).
+// One cyclic-reduction level with stride D, split into the matrix part (the
+// row (A, B, C) of every lane and the multipliers k1, k2 of the level, which
+// depend on the pole only) and the right-hand-side part (both right-hand
+// sides of one state, with the level's multipliers).
 template <int KIND, int D>
-__device__ __forceinline__ void pcr_level(cd& Ac, cd& Bc, cd& Cc, cd& Du, cd& Dw, int l, int P, int lane) {
+__device__ __forceinline__ void pcr_matrix(cd& Ac, cd& Bc, cd& Cc, cd& k1, cd& k2, int l, int P, int lane) {
     typedef Mover<KIND, D> Mv;
     // neighbours outside the chain's group: multipliers are zero.  Each moved
     // value is consumed before the next move (keeps few values live).
     cd lo, hi;
     Mv::both(crcp_newton(Bc), lane, lo, hi);
-    const cd k1 = (l >= D) ? cmul(Ac, lo) : mk(0, 0);
-    const cd k2 = (l + D < P) ? cmul(Cc, hi) : mk(0, 0);
+    k1 = (l >= D) ? cmul(Ac, lo) : mk(0, 0);
+    k2 = (l + D < P) ? cmul(Cc, hi) : mk(0, 0);
     Mv::both(Cc, lane, lo, hi);
     Bc = cfms(Bc, k1, lo);
     Cc = cneg(cmul(k2, hi));
     Mv::both(Ac, lane, lo, hi);
     Bc = cfms(Bc, k2, hi);
     Ac = cneg(cmul(k1, lo));
+}
+template <int KIND, int D>
+__device__ __forceinline__ void pcr_rhs(cd k1, cd k2, cd& Du, cd& Dw, int lane) {
+    typedef Mover<KIND, D> Mv;
+    cd lo, hi;
     Mv::both(Du, lane, lo, hi);
     Du = cfms(cfms(Du, k1, lo), k2, hi);
     Mv::both(Dw, lane, lo, hi);
     Dw = cfms(cfms(Dw, k1, lo), k2, hi);
 }
 
-// One work item: chain p of order m, one state, a pole range.  SE elements per
-// lane (even, compile time); PH fixes the element types: element t of every
-// lane is a divergence element iff (t + PH) is odd.
+// LDS of a work item.  Staged per chain position, as planes of doubles
+// [t][plane][slot]: th, om, c_left, c_right, then Re/Im of the chain variable
+// and of Phi for each of the item's R states (each state's block of four
+// planes SBLK doubles long).  With R > 1 every wave also
+// owns a factorisation region: per interior element t and wave lane the
+// pivot reciprocal q_t and, where LDS allows, the running product pi_t
+// (NQ >= 4) and the left spike gv_t (NQ = 6), [t][quantity][64]; then per
+// cyclic-reduction level the multipliers k1, k2 [level][4][64] and the
+// interface pivot's reciprocal [2][64].
+template <int SE, int KIND, int W, int R>
+struct SolveLds {
+    static constexpr int PS = (KIND == kMoveRow) ? 16 : (KIND == kMovePair) ? 32 : 64;  // slots per position
+    static constexpr int NI = SE - 1;
+    static constexpr int LV = (KIND == kMoveRow) ? 4 : (KIND == kMovePair) ? 5 : 6;    // levels for P <= PS
+    static constexpr int SPAD = 0;                                                      // state block pad
+    static constexpr int SBLK = 4 * PS + SPAD;                                          // state block
+    static constexpr int POS = 4 * PS + R * SBLK;                                       // per position
+    static constexpr int kStaged = POS * SE;                                            // doubles
+    // two waves per SIMD (two workgroups of four waves per CU) where the
+    // registers allow it: tiles of up to 6 elements, and 8 with one state per
+    // item; the others take a CU's whole LDS (160 KB)
+    static constexpr int kWavesPerSimd = (SE <= 6 || (SE == 8 && R == 1)) ? 2 : 1;
+    static constexpr int kMaxDoubles = ((kWavesPerSimd == 2 ? 80 : 160) * 1024 - 64) / 8;
+    static constexpr int region(int nq) { return 64 * (NI * nq + 4 * LV + 2); }
+    static constexpr int total(int nq) { return kStaged + (R > 1 ? W * region(nq) : 0); }
+    // the reuse passes recompute the spike and the running product from the
+    // pivots (12 VALU instructions per element), which measured faster than
+    // reading them (LDS reads, not VALU issue, bound those passes)
+    static constexpr int NQ = 2;
+    static constexpr int kRegion = R > 1 ? region(NQ) : 0;
+    static constexpr int kDoubles = total(NQ);
+    static_assert(kDoubles <= kMaxDoubles, "work item does not fit in LDS");
+};
+
+// One work item: chain p of order m, the R states [tile R, tile R + R), a
+// pole range.  SE elements per lane (even, compile time); PH fixes the
+// element types: element t of every lane is a divergence element iff
+// (t + PH) is odd.
 //
 // Per pole each lane runs one forward sweep over its interior elements
 // t = 0..SE-2 that at once forms the pivots q, multipliers e = q c, the
@@ -233,16 +274,29 @@ __device__ __forceinline__ void pcr_level(cd& Ac, cd& Bc, cd& Cc, cd& Du, cd& Dw
 // chain's P lanes, matrix and both right-hand sides in the same levels, and a
 // reverse sweep recovers the interior with both interface values.
 //
+// States (R > 1): the factorisation (q, e, gv, pi, and the reduction's
+// multipliers) depends on the pole and the chain only.  Group g of a wave
+// keeps state g mod R for the whole item, and the groups form blocks of R.
+// For each batch of the wave's G poles, pass 0 has every group solve its own
+// pole for its own state, computing the factorisation and publishing it in
+// the wave's LDS region; passes 1..R-1 have group g solve the pole of group
+// blk R + (g + j) mod R of its block for its own state, reading that
+// factorisation instead of recomputing it.  Each pole is so solved for all R
+// states with one factorisation.
+//
 // Mirrored right-hand side: with jv = -(-1)^n the J sign of vorticity and
 // divergence, the staged chain data v gives conj(J v) = jv conj(v) on the
 // chain and -jv conj(r^Phi) on Phi.  Since SE is even, jv = j0 (-1)^t with one
 // sign j0 per item; the solve is linear, so j0 is dropped from the right-hand
 // side and cancels against the same factor of J on the output.  What remains
 // is (-1)^t on input and output.
-template <int SE, int PH, bool ACCUM, int KIND, int W>
+template <int SE, int PH, bool ACCUM, int KIND, int W, int R>
 __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, const MInfo& mi, double* sm) {
     static_assert(SE % 2 == 0, "elements per lane must be even");
+    static_assert(R == 1 || R == 2 || R == 4, "states per item");
+    typedef SolveLds<SE, KIND, W, R> Lds;
     constexpr int NI = SE - 1;  // interior elements 0 .. SE-2; interface SE-1
+    constexpr int PS = Lds::PS, POS = Lds::POS, NQ = Lds::NQ;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int P = (KIND == kMovePair) ? 32 : mi.P;
@@ -260,36 +314,45 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     // slots per chunk fixed at compile time so that every LDS offset below is
     // an immediate
     const int slot = (KIND == kMovePair) ? (lane & 31) : l;
-    constexpr int PS = (KIND == kMoveRow) ? 16 : (KIND == kMovePair) ? 32 : 64;
-    const int st = it.tile;
+    const int st0 = it.tile * R;
     const int npos = P * SE;
+    const int sg_state = g & (R - 1);   // this group's state within the item
+    const int blk = g / R;              // its block of R groups
 
-    // ---- stage the item's constants and right-hand sides in LDS as eight
-    // planes of doubles per position, [t][plane][slot], so that the lanes of a
-    // row read consecutive 8-byte words (8-byte reads issue far faster here than
-    // 16-byte ones): th, om, c_left, c_right, Re/Im r_var, Re/Im r_Phi
+    // ---- stage the item's constants and right-hand sides in LDS as planes of
+    // doubles per position, [t][plane][slot], so that the lanes of a row read
+    // consecutive 8-byte words (8-byte reads issue far faster here than
+    // 16-byte ones)
     double2* c = reinterpret_cast<double2*>(sm);
     for (int j = tid; j < npos; j += blockDim.x) {
         const int l2 = j / SE, t2 = j - l2 * SE;
         const int s2 = (KIND == kMovePair) ? ((l2 >> 1) + 16 * (l2 & 1)) : l2;
         const int n = n0 + j;
-        double2 v0 = make_double2(0.0, 0.0), v1 = v0, v2 = v0, v3 = v0;
-        if (j < L) {
-            const long long i = mi.spec_off + (n - m);
+        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+        const bool in = j < L;
+        const long long i = mi.spec_off + (n - m);
+        if (in) {
             v0 = make_double2(A.th[i], A.om[i]);
             v1 = make_double2((j > 0) ? A.cc[i] : 0.0, (n < A.T) ? A.cc[i + 1] : 0.0);
-            v2 = A.ch_var[st * A.var_stride + mi.slot_base + (long long)p * L + j];
-            if ((n + p) & 1) v3 = A.ch_phi[st * A.nspec + i];
         }
-        double* o = sm + (size_t)(t2 * 8) * PS + s2;
+        double* o = sm + (size_t)t2 * POS + s2;
         o[0] = v0.x;
         o[PS] = v0.y;
         o[2 * PS] = v1.x;
         o[3 * PS] = v1.y;
-        o[4 * PS] = v2.x;
-        o[5 * PS] = v2.y;
-        o[6 * PS] = v3.x;
-        o[7 * PS] = v3.y;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            double2 v2 = make_double2(0.0, 0.0), v3 = v2;
+            if (in) {
+                v2 = A.ch_var[(st0 + q) * A.var_stride + mi.slot_base + (long long)p * L + j];
+                if ((n + p) & 1) v3 = A.ch_phi[(st0 + q) * A.nspec + i];
+            }
+            double* os = o + 4 * PS + q * Lds::SBLK;
+            os[0] = v2.x;
+            os[PS] = v2.y;
+            os[2 * PS] = v3.x;
+            os[3 * PS] = v3.y;
+        }
     }
     __syncthreads();
 
@@ -310,165 +373,71 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         double th, om, cl, cr;
         cd rv, rp;
     };
+    const double* cbase = sm + slot;                                   // planes 0..3
+    const double* sbase = sm + slot + 4 * PS + sg_state * Lds::SBLK;   // this group's state
     auto fetch = [&](int t, bool with_cr) {
-        const double* o = sm + (size_t)(t * 8) * PS + slot;
+        const double* o = cbase + (size_t)t * POS;
+        const double* os = sbase + (size_t)t * POS;
         Pos x;
         x.th = o[0];
         x.cl = o[2 * PS];
         x.cr = with_cr ? o[3 * PS] : 0.0;
-        x.rv = cd{o[4 * PS], o[5 * PS]};
+        x.rv = cd{os[0], os[PS]};
         if ((PH + t) & 1) {
             x.om = o[PS];
-            x.rp = cd{o[6 * PS], o[7 * PS]};
+            x.rp = cd{os[2 * PS], os[3 * PS]};
         } else {
             x.om = 0.0;
             x.rp = mk(0, 0);
         }
         return x;
     };
+    // the wave's factorisation region (R > 1)
+    double* reg = sm + Lds::kStaged + wave * Lds::kRegion;
+    constexpr int kPcr = 64 * NI * NQ;        // start of the reduction's multipliers
+    constexpr int kIb = kPcr + 64 * 4 * Lds::LV;
+
     // Latency hiding where registers allow (row groups): the pole and its
     // reciprocal are fetched one iteration ahead, the staged data of position
     // t + 1 before the work on t, and scheduling barriers keep these reads
     // where they are.  The row-pair kind has no registers to spare for it.
-    constexpr bool kAhead = (KIND == kMoveRow);
+    constexpr bool kAhead = (KIND == kMoveRow) || (KIND == kMovePair && Lds::kWavesPerSimd == 1 && R > 1);
+    // pole solved by this group in pass j of the batch starting at kb
+    auto pole_of = [&](int kb, int j) { return kb + wave * G + blk * R + ((sg_state + j) & (R - 1)); };
     cd al_n = mk(0, 0), ai_n = mk(0, 0);
     if constexpr (kAhead) {
-        const int k = it.k0 + wave * G + g;
+        const int k = pole_of(it.k0, 0);
         const PoleData& pn = A.poles[k < it.k1 ? k : it.k0];
         al_n = cd{pn.al.x, pn.al.y};
         ai_n = cd{pn.ai.x, pn.ai.y};
     }
 
-    for (int kb = it.k0; kb < it.k1; kb += stride) {
-        if (kb + wave * G >= it.k1) continue;  // this wave has no pole left (uniform)
-        const int k = kb + wave * G + g;
-        const bool act = k < it.k1;
-        const PoleData& pd = A.poles[act ? k : it.k0];
-        cd al, ai;
-        if constexpr (kAhead) {
-            al = al_n;
-            ai = ai_n;
-            const int kn = k + stride;
-            const PoleData& pn = A.poles[kn < it.k1 ? kn : it.k0];
-            al_n = cd{pn.al.x, pn.al.y};
-            ai_n = cd{pn.ai.x, pn.ai.y};
-            __builtin_amdgcn_sched_barrier(0);
+    // element of position t: couplings and both right-hand sides (the
+    // mirrored one as described above); f = om / alpha on divergence rows
+    auto element_rhs = [&](int t, const Pos& x, const cd& ai, double& ca, double& cb, cd& du, cd& dw, cd& f) {
+        const double sg = ((PH + t) & 1) ? 1.0 : -1.0;  // divergence rows +, vorticity rows -
+        const double ts = (t & 1) ? -1.0 : 1.0;         // (-1)^t
+        ca = sg * x.cl;
+        cb = sg * x.cr;
+        if ((PH + t) & 1) {
+            // divergence element, Phi eliminated: right-hand side r_div - (om/alpha) r_Phi
+            f = cscale(ai, x.om);
+            du = cfms(x.rv, f, x.rp);
+            const double wr = fma(f.r, x.rp.r, fma(f.i, x.rp.i, x.rv.r));
+            const double wi = fma(f.i, x.rp.r, fma(-f.r, x.rp.i, -x.rv.i));
+            dw = cd{ts * wr, ts * wi};
         } else {
-            al = cd{pd.al.x, pd.al.y};
-            ai = cd{pd.ai.x, pd.ai.y};
+            f = mk(0, 0);
+            du = x.rv;
+            dw = cd{ts * x.rv.r, -ts * x.rv.i};
         }
+    };
 
-        cd e[NI], gv[NI], Gu[NI], Gw[NI];
-        cd pi = mk(1, 0), v0 = mk(0, 0), w0 = mk(0, 0), g0u = mk(0, 0), g0w = mk(0, 0);
-        cd qprev = mk(0, 0);
-        double cbprev = 0.0;
-        // element of position t: diagonal b, couplings, and both right-hand
-        // sides (the mirrored one as described above)
-        auto element = [&](int t, const Pos& x, cd& b, double& ca, double& cb, cd& du, cd& dw) {
-            const double sg = ((PH + t) & 1) ? 1.0 : -1.0;  // divergence rows +, vorticity rows -
-            const double ts = (t & 1) ? -1.0 : 1.0;         // (-1)^t
-            ca = sg * x.cl;
-            cb = sg * x.cr;
-            if ((PH + t) & 1) {
-                // divergence element, Phi eliminated: diagonal alpha + i th + om^2/alpha,
-                // right-hand side r_div - (om/alpha) r_Phi
-                const double om = x.om;
-                const cd f = cscale(ai, om);
-                b = mk(fma(om, f.r, al.r), al.i + fma(om, f.i, x.th));
-                du = cfms(x.rv, f, x.rp);
-                const double wr = fma(f.r, x.rp.r, fma(f.i, x.rp.i, x.rv.r));
-                const double wi = fma(f.i, x.rp.r, fma(-f.r, x.rp.i, -x.rv.i));
-                dw = cd{ts * wr, ts * wi};
-            } else {
-                b = mk(al.r, al.i + x.th);
-                du = x.rv;
-                dw = cd{ts * x.rv.r, -ts * x.rv.i};
-            }
-        };
-        // forward sweep (with kAhead the next position's data is read before
-        // this one's work)
-        Pos cur;
-        if constexpr (kAhead) cur = fetch(0, false);
-#pragma unroll
-        for (int t = 0; t < NI; ++t) {
-            Pos nxt;
-            if constexpr (kAhead) {
-                nxt = fetch(t + 1, t + 1 == SE - 1);
-                __builtin_amdgcn_sched_barrier(0);
-                cur.cr = nxt.cl;
-            } else {
-                cur = fetch(t, true);
-            }
-            cd b, du, dw;
-            double ca, cb;
-            element(t, cur, b, ca, cb, du, dw);
-            if (t > 0) b = csubs(b, ca * cbprev, qprev);
-            const cd q = crcp_newton(b);
-            e[t] = cscale(q, cb);
-            if (t == 0) {
-                gv[0] = cscale(q, ca);
-                Gu[0] = cmul(q, du);
-                Gw[0] = cmul(q, dw);
-            } else {
-                gv[t] = cmul(q, cscale(gv[t - 1], -ca));
-                Gu[t] = cmul(q, csubs(du, ca, Gu[t - 1]));
-                Gw[t] = cmul(q, csubs(dw, ca, Gw[t - 1]));
-            }
-            v0 = cfma(v0, pi, gv[t]);
-            g0u = cfma(g0u, pi, Gu[t]);
-            g0w = cfma(g0w, pi, Gw[t]);
-            if (t == NI - 1) w0 = cmul(pi, e[t]);
-            pi = cneg(cmul(pi, e[t]));
-            qprev = q;
-            cbprev = cb;
-            if constexpr (kAhead) cur = nxt;
-        }
-
-        // this pole's weights: read here, used after the interface solve
-        cd wx = cd{pd.wx.x, pd.wx.y}, wxa = cd{pd.wxa.x, pd.wxa.y};
-        cd wyE = cd{pd.wy.x, pd.wy.y}, wyaE = cd{pd.wya.x, pd.wya.y};
-        if constexpr (kAhead) __builtin_amdgcn_sched_barrier(0);
-
-        // interface row -> tridiagonal system over the P lanes of the chain;
-        // the right neighbour's values enter with cI, which is zero at a chain end
-        cd bI, dIu, dIw;
-        double aI, cI;
-        if constexpr (!kAhead) cur = fetch(SE - 1, true);
-        element(SE - 1, cur, bI, aI, cI, dIu, dIw);
-        typedef Mover<KIND, 1> M1;
-        const cd vN = M1::above(v0, lane), wN = M1::above(w0, lane);
-        const cd guN = M1::above(g0u, lane), gwN = M1::above(g0w, lane);
-        cd Ac = cneg(cscale(gv[NI - 1], aI));
-        cd Bc = csubs(csubs(bI, aI, e[NI - 1]), cI, vN);
-        cd Cc = cneg(cscale(wN, cI));
-        cd Du = csubs(csubs(dIu, aI, Gu[NI - 1]), cI, guN);
-        cd Dw = csubs(csubs(dIw, aI, Gw[NI - 1]), cI, gwN);
-
-        // cyclic reduction over the lanes of the chain
-        if constexpr (KIND == kMovePair) {
-            pcr_level<KIND, 1>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            pcr_level<KIND, 2>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            pcr_level<KIND, 4>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            pcr_level<KIND, 8>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            pcr_level<KIND, 16>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-        } else {
-            if (1 < P) pcr_level<KIND, 1>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            if (2 < P) pcr_level<KIND, 2>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            if (4 < P) pcr_level<KIND, 4>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            if (8 < P) pcr_level<KIND, 8>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            if constexpr (KIND == kMoveBperm) {
-                if (16 < P) pcr_level<KIND, 16>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-                if (32 < P) pcr_level<KIND, 32>(Ac, Bc, Cc, Du, Dw, l, P, lane);
-            }
-        }
-        const cd iB = crcp_newton(Bc);
-        const cd Xu = cmul(Du, iB), Xw = cmul(Dw, iB);
-        // the left neighbour's interface values (enter through gv, zero at a chain start)
-        const cd XLu = M1::below(Xu, lane), XLw = M1::below(Xw, lane);
-
-        // reverse sweep with both interface values; weighted sums.  The mirrored
-        // solution enters conjugated with (-1)^t on the chain variable and
-        // -(-1)^t on Phi.
+    // reverse sweep with both interface values and the weighted sums.  The
+    // mirrored solution enters conjugated with (-1)^t on the chain variable
+    // and -(-1)^t on Phi.
+    auto back_and_accumulate = [&](const cd* e, const cd* gv, const cd* Gu, const cd* Gw, cd Xu, cd Xw, cd XLu,
+                                   cd XLw, cd wx, cd wxa, cd wyE, cd wyaE, bool act) {
         wyaE = cneg(wyaE);
         if (!act) wx = wxa = wyE = wyaE = mk(0, 0);
         cd xu = Xu, xw = Xw;
@@ -487,10 +456,295 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
                 }
             }
         }
+    };
+    typedef Mover<KIND, 1> M1;
+
+    for (int kb = it.k0; kb < it.k1; kb += stride) {
+        if (kb + wave * G >= it.k1) continue;  // this wave has no pole left (uniform)
+        // ================= pass 0: own pole, factorisation computed (and published)
+        {
+            const int k = pole_of(kb, 0);
+            const bool act = k < it.k1;
+            const PoleData& pd = A.poles[act ? k : it.k0];
+            cd al, ai;
+            if constexpr (kAhead) {
+                al = al_n;
+                ai = ai_n;
+                const int kn = (R > 1) ? pole_of(kb, 1) : pole_of(kb + stride, 0);
+                const PoleData& pn = A.poles[kn < it.k1 ? kn : it.k0];
+                al_n = cd{pn.al.x, pn.al.y};
+                ai_n = cd{pn.ai.x, pn.ai.y};
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+                al = cd{pd.al.x, pd.al.y};
+                ai = cd{pd.ai.x, pd.ai.y};
+            }
+
+            cd e[NI], gv[NI], Gu[NI], Gw[NI];
+            cd pi = mk(1, 0), v0 = mk(0, 0), w0 = mk(0, 0), g0u = mk(0, 0), g0w = mk(0, 0);
+            cd qprev = mk(0, 0);
+            double cbprev = 0.0;
+            // element of position t: diagonal b, couplings, right-hand sides
+            auto element = [&](int t, const Pos& x, cd& b, double& ca, double& cb, cd& du, cd& dw) {
+                cd f;
+                element_rhs(t, x, ai, ca, cb, du, dw, f);
+                if ((PH + t) & 1) {
+                    // divergence element: diagonal alpha + i th + om^2/alpha
+                    b = mk(fma(x.om, f.r, al.r), al.i + fma(x.om, f.i, x.th));
+                } else {
+                    b = mk(al.r, al.i + x.th);
+                }
+            };
+            Pos cur;
+            if constexpr (kAhead) cur = fetch(0, false);
+#pragma unroll
+            for (int t = 0; t < NI; ++t) {
+                Pos nxt;
+                if constexpr (kAhead) {
+                    nxt = fetch(t + 1, t + 1 == SE - 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    cur.cr = nxt.cl;
+                } else {
+                    cur = fetch(t, true);
+                }
+                cd b, du, dw;
+                double ca, cb;
+                element(t, cur, b, ca, cb, du, dw);
+                if (t > 0) b = csubs(b, ca * cbprev, qprev);
+                const cd q = crcp_newton(b);
+                e[t] = cscale(q, cb);
+                if (t == 0) {
+                    gv[0] = cscale(q, ca);
+                    Gu[0] = cmul(q, du);
+                    Gw[0] = cmul(q, dw);
+                } else {
+                    gv[t] = cmul(q, cscale(gv[t - 1], -ca));
+                    Gu[t] = cmul(q, csubs(du, ca, Gu[t - 1]));
+                    Gw[t] = cmul(q, csubs(dw, ca, Gw[t - 1]));
+                }
+                if constexpr (R > 1) {
+                    double* r = reg + (t * NQ) * 64 + lane;
+                    r[0] = q.r;
+                    r[64] = q.i;
+                    if constexpr (NQ >= 4) {
+                        r[128] = pi.r;
+                        r[192] = pi.i;
+                    }
+                    if constexpr (NQ >= 6) {
+                        r[256] = gv[t].r;
+                        r[320] = gv[t].i;
+                    }
+                }
+                v0 = cfma(v0, pi, gv[t]);
+                g0u = cfma(g0u, pi, Gu[t]);
+                g0w = cfma(g0w, pi, Gw[t]);
+                if (t == NI - 1) w0 = cmul(pi, e[t]);
+                pi = cneg(cmul(pi, e[t]));
+                qprev = q;
+                cbprev = cb;
+                if constexpr (kAhead) cur = nxt;
+            }
+
+            // this pole's weights: read here, used after the interface solve
+            cd wx = cd{pd.wx.x, pd.wx.y}, wxa = cd{pd.wxa.x, pd.wxa.y};
+            cd wyE = cd{pd.wy.x, pd.wy.y}, wyaE = cd{pd.wya.x, pd.wya.y};
+            if constexpr (kAhead) __builtin_amdgcn_sched_barrier(0);
+
+            // interface row -> tridiagonal system over the P lanes of the chain;
+            // the right neighbour's values enter with cI, which is zero at a chain end
+            cd bI, dIu, dIw;
+            double aI, cI;
+            if constexpr (!kAhead) cur = fetch(SE - 1, true);
+            element(SE - 1, cur, bI, aI, cI, dIu, dIw);
+            const cd vN = M1::above(v0, lane), wN = M1::above(w0, lane);
+            const cd guN = M1::above(g0u, lane), gwN = M1::above(g0w, lane);
+            cd Ac = cneg(cscale(gv[NI - 1], aI));
+            cd Bc = csubs(csubs(bI, aI, e[NI - 1]), cI, vN);
+            cd Cc = cneg(cscale(wN, cI));
+            cd Du = csubs(csubs(dIu, aI, Gu[NI - 1]), cI, guN);
+            cd Dw = csubs(csubs(dIw, aI, Gw[NI - 1]), cI, gwN);
+
+            // cyclic reduction over the lanes of the chain
+            auto level = [&](auto dconst, int lev) {
+                constexpr int D = decltype(dconst)::value;
+                cd k1, k2;
+                pcr_matrix<KIND, D>(Ac, Bc, Cc, k1, k2, l, P, lane);
+                pcr_rhs<KIND, D>(k1, k2, Du, Dw, lane);
+                if constexpr (R > 1) {
+                    double* r = reg + kPcr + (lev * 4) * 64 + lane;
+                    r[0] = k1.r;
+                    r[64] = k1.i;
+                    r[128] = k2.r;
+                    r[192] = k2.i;
+                }
+            };
+            typedef std::integral_constant<int, 1> D1;
+            typedef std::integral_constant<int, 2> D2;
+            typedef std::integral_constant<int, 4> D4;
+            typedef std::integral_constant<int, 8> D8;
+            typedef std::integral_constant<int, 16> D16;
+            typedef std::integral_constant<int, 32> D32;
+            if constexpr (KIND == kMovePair) {
+                level(D1{}, 0);
+                level(D2{}, 1);
+                level(D4{}, 2);
+                level(D8{}, 3);
+                level(D16{}, 4);
+            } else {
+                if (1 < P) level(D1{}, 0);
+                if (2 < P) level(D2{}, 1);
+                if (4 < P) level(D4{}, 2);
+                if (8 < P) level(D8{}, 3);
+                if constexpr (KIND == kMoveBperm) {
+                    if (16 < P) level(D16{}, 4);
+                    if (32 < P) level(D32{}, 5);
+                }
+            }
+            const cd iB = crcp_newton(Bc);
+            if constexpr (R > 1) {
+                double* r = reg + kIb + lane;
+                r[0] = iB.r;
+                r[64] = iB.i;
+            }
+            const cd Xu = cmul(Du, iB), Xw = cmul(Dw, iB);
+            // the left neighbour's interface values (enter through gv, zero at a chain start)
+            const cd XLu = M1::below(Xu, lane), XLw = M1::below(Xw, lane);
+            back_and_accumulate(e, gv, Gu, Gw, Xu, Xw, XLu, XLw, wx, wxa, wyE, wyaE, act);
+        }
+
+        // ================= passes 1..R-1: the block's other poles, factorisation read
+        if constexpr (R > 1) {
+#pragma unroll 1
+            for (int j = 1; j < R; ++j) {
+                const int src = blk * R + ((sg_state + j) & (R - 1));   // group that factorised this pole
+                const int k = kb + wave * G + src;
+                const bool act = k < it.k1;
+                const PoleData& pd = A.poles[act ? k : it.k0];
+                cd ai;
+                if constexpr (kAhead) {
+                    ai = ai_n;
+                    const int kn = (j + 1 < R) ? pole_of(kb, j + 1) : pole_of(kb + stride, 0);
+                    const PoleData& pn = A.poles[kn < it.k1 ? kn : it.k0];
+                    al_n = cd{pn.al.x, pn.al.y};
+                    ai_n = cd{pn.ai.x, pn.ai.y};
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+                    ai = cd{pd.ai.x, pd.ai.y};
+                }
+                const double* rs = reg + lane + (src - g) * P;   // the source group's lane for chain lane l
+
+                cd e[NI], gv[NI], Gu[NI], Gw[NI];
+                cd pi = mk(1, 0), g0u = mk(0, 0), g0w = mk(0, 0);
+                // published factorisation of element t: pivot, and where
+                // stored, running product and spike
+                struct Fac {
+                    cd q, pi, gv;
+                };
+                auto ffetch = [&](int t) {
+                    const double* r = rs + (t * NQ) * 64;
+                    Fac x;
+                    x.q = cd{r[0], r[64]};
+                    if constexpr (NQ >= 4) x.pi = cd{r[128], r[192]};
+                    if constexpr (NQ >= 6) x.gv = cd{r[256], r[320]};
+                    return x;
+                };
+                Pos cur;
+                Fac fcur;
+                if constexpr (kAhead) {
+                    cur = fetch(0, false);
+                    fcur = ffetch(0);
+                }
+#pragma unroll
+                for (int t = 0; t < NI; ++t) {
+                    Pos nxt;
+                    Fac fnxt;
+                    if constexpr (kAhead) {
+                        nxt = fetch(t + 1, t + 1 == SE - 1);
+                        if (t + 1 < NI) fnxt = ffetch(t + 1);
+                        __builtin_amdgcn_sched_barrier(0);
+                        cur.cr = nxt.cl;
+                    } else {
+                        cur = fetch(t, true);
+                        fcur = ffetch(t);
+                    }
+                    const cd q = fcur.q;
+                    cd du, dw, f;
+                    double ca, cb;
+                    element_rhs(t, cur, ai, ca, cb, du, dw, f);
+                    e[t] = cscale(q, cb);
+                    if constexpr (NQ >= 6) {
+                        gv[t] = fcur.gv;
+                    } else {
+                        gv[t] = (t == 0) ? cscale(q, ca) : cmul(q, cscale(gv[t - 1], -ca));
+                    }
+                    if constexpr (NQ >= 4) pi = fcur.pi;
+                    if (t == 0) {
+                        Gu[0] = cmul(q, du);
+                        Gw[0] = cmul(q, dw);
+                    } else {
+                        Gu[t] = cmul(q, csubs(du, ca, Gu[t - 1]));
+                        Gw[t] = cmul(q, csubs(dw, ca, Gw[t - 1]));
+                    }
+                    g0u = cfma(g0u, pi, Gu[t]);
+                    g0w = cfma(g0w, pi, Gw[t]);
+                    if constexpr (NQ < 4) pi = cneg(cmul(pi, e[t]));
+                    if constexpr (kAhead) {
+                        cur = nxt;
+                        fcur = fnxt;
+                    }
+                }
+                // first level's multipliers, read ahead of their use
+                cd k1n = cd{rs[kPcr], rs[kPcr + 64]}, k2n = cd{rs[kPcr + 128], rs[kPcr + 192]};
+                cd wx = cd{pd.wx.x, pd.wx.y}, wxa = cd{pd.wxa.x, pd.wxa.y};
+                cd wyE = cd{pd.wy.x, pd.wy.y}, wyaE = cd{pd.wya.x, pd.wya.y};
+                if constexpr (kAhead) __builtin_amdgcn_sched_barrier(0);
+
+                cd dIu, dIw, fI;
+                double aI, cI;
+                if constexpr (!kAhead) cur = fetch(SE - 1, true);
+                element_rhs(SE - 1, cur, ai, aI, cI, dIu, dIw, fI);
+                const cd guN = M1::above(g0u, lane), gwN = M1::above(g0w, lane);
+                cd Du = csubs(csubs(dIu, aI, Gu[NI - 1]), cI, guN);
+                cd Dw = csubs(csubs(dIw, aI, Gw[NI - 1]), cI, gwN);
+                auto level = [&](auto dconst, int lev) {
+                    constexpr int D = decltype(dconst)::value;
+                    const cd k1 = k1n, k2 = k2n;
+                    // the next level's (the last level reads its own again)
+                    const int ln = (lev + 1 < Lds::LV) ? lev + 1 : lev;
+                    const double* r = rs + kPcr + (ln * 4) * 64;
+                    k1n = cd{r[0], r[64]};
+                    k2n = cd{r[128], r[192]};
+                    pcr_rhs<KIND, D>(k1, k2, Du, Dw, lane);
+                };
+                typedef std::integral_constant<int, 1> D1;
+                typedef std::integral_constant<int, 2> D2;
+                typedef std::integral_constant<int, 4> D4;
+                typedef std::integral_constant<int, 8> D8;
+                typedef std::integral_constant<int, 16> D16;
+                if constexpr (KIND == kMovePair) {
+                    level(D1{}, 0);
+                    level(D2{}, 1);
+                    level(D4{}, 2);
+                    level(D8{}, 3);
+                    level(D16{}, 4);
+                } else {
+                    static_assert(KIND == kMoveRow, "states share factorisations only in row and row-pair tilings");
+                    if (1 < P) level(D1{}, 0);
+                    if (2 < P) level(D2{}, 1);
+                    if (4 < P) level(D4{}, 2);
+                    if (8 < P) level(D8{}, 3);
+                }
+                const cd iB = cd{rs[kIb], rs[kIb + 64]};
+                const cd Xu = cmul(Du, iB), Xw = cmul(Dw, iB);
+                const cd XLu = M1::below(Xu, lane), XLw = M1::below(Xw, lane);
+                back_and_accumulate(e, gv, Gu, Gw, Xu, Xw, XLu, XLw, wx, wxa, wyE, wyaE, act);
+            }
+        }
     }
 
-    // sum the G groups of each wave (same chain lanes) in a fixed tree order
-    for (int off = 32; off >= P; off >>= 1) {
+    // sum the groups of each wave that hold the same state (same chain lanes,
+    // groups g and g + R, g + 2R, ...) in a fixed tree order
+    for (int off = 32; off >= R * P; off >>= 1) {
         const int src = (lane + off) & 63;
 #pragma unroll
         for (int t = 0; t < SE; ++t) {
@@ -498,14 +752,15 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
             if ((PH + t) & 1) ap[t] = cadd(ap[t], shfl(ap[t], src));
         }
     }
-    // then the waves, in order, through LDS (reusing the staging area)
+    // then the waves, in order, through LDS (reusing the staging area):
+    // acc[state][2][SE][P], groups 0..R-1 of each wave hold states 0..R-1
     __syncthreads();
-    double2* acc = c;  // [2][SE][P]
+    double2* acc = c;
     for (int wv = 0; wv < W; ++wv) {
-        if (wave == wv && g == 0) {
+        if (wave == wv && g < R) {
 #pragma unroll
             for (int t = 0; t < SE; ++t) {
-                const int o0 = t * P + l, o1 = (SE + t) * P + l;
+                const int o0 = ((g * 2 + 0) * SE + t) * P + l, o1 = ((g * 2 + 1) * SE + t) * P + l;
                 double2 a0 = make_double2(av[t].r, av[t].i);
                 double2 a1 = make_double2(ap[t].r, ap[t].i);
                 if (wv > 0) {
@@ -520,13 +775,14 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < 2 * L; idx += blockDim.x) {
-        const int plane = idx / L;
-        const int j = idx - plane * L;
+    for (int idx = tid; idx < 2 * R * L; idx += blockDim.x) {
+        const int sp = idx / L;            // state * 2 + plane
+        const int plane = sp & 1;
+        const int j = idx - sp * L;
         const int l2 = j / SE, t2 = j - l2 * SE;
         if (plane == 1 && !(((PH + t2) & 1) != 0)) continue;
-        const double2 v = acc[(plane * SE + t2) * P + l2];
-        const long long o = it.part_off + ((long long)plane * L + j);
+        const double2 v = acc[(sp * SE + t2) * P + l2];
+        const long long o = it.part_off + ((long long)sp * L + j);
         if (ACCUM) {
             const double2 old = A.part[o];
             A.part[o] = make_double2(old.x + v.x, old.y + v.y);
@@ -536,25 +792,26 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, const Item& it, c
     }
 }
 
-template <int SE, bool ACCUM, int KIND, int W>
+template <int SE, bool ACCUM, int KIND, int W, int R>
 __device__ __forceinline__ void run_item(const SolveArgs& A, int idx, double* sm) {
     const Item it = A.items[idx];
     const MInfo mi = A.minfo[it.m];
-    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, KIND, W>(A, it, mi, sm);
-    else solve_item<SE, 0, ACCUM, KIND, W>(A, it, mi, sm);
+    if ((mi.n0 + it.p) & 1) solve_item<SE, 1, ACCUM, KIND, W, R>(A, it, mi, sm);
+    else solve_item<SE, 0, ACCUM, KIND, W, R>(A, it, mi, sm);
 }
 
 // One workgroup per item (counter == null), or persistent: a grid of resident
 // workgroups takes items [item0, item0 + nitems) from an atomic counter that
 // starts at zero, until none is left (every workgroup then leaves the loop).
-// Tiles of up to 8 elements per lane are held to 256 registers (two waves per
-// SIMD); larger ones use the whole register file (10 would spill at 256).
-template <int SE, bool ACCUM, int KIND, int W>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(SE <= 8 ? 2 : 1)))
+// Small tiles are held to 256 registers (two waves per SIMD); larger ones use
+// the whole register file (10 elements would spill at 256).
+template <int SE, bool ACCUM, int KIND, int W, int R>
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(SolveLds<SE, KIND, W, R>::kWavesPerSimd)))
 k_solve(const SolveArgs A, int item0, int nitems, int* counter) {
     extern __shared__ double sm[];
     if (counter == nullptr) {
-        run_item<SE, ACCUM, KIND, W>(A, item0 + blockIdx.x, sm);
+        run_item<SE, ACCUM, KIND, W, R>(A, item0 + blockIdx.x, sm);
         return;
     }
     __shared__ int next;
@@ -564,7 +821,7 @@ k_solve(const SolveArgs A, int item0, int nitems, int* counter) {
         const int i = next;
         __syncthreads();
         if (i < 0 || i >= nitems) break;
-        run_item<SE, ACCUM, KIND, W>(A, item0 + i, sm);
+        run_item<SE, ACCUM, KIND, W, R>(A, item0 + i, sm);
     }
 }
 
@@ -610,7 +867,7 @@ struct ReduceArgs {
     double2* ch_var_out;  // chain layout (next step), or null
     double2* ch_phi_out;
     double2* u_out;       // physical layout (last step), or null
-    int ST, ntiles, S, invert_scale;
+    int S, invert_scale;
     long long nspec, var_stride, nslots;
     cd g00, gphi;
 };
@@ -646,12 +903,11 @@ __global__ void k_reduce(const ReduceArgs R) {
     const int p = (int)(rel / mi.L);
     const int j = (int)(rel - (long long)p * mi.L);
     const int n = mi.n0 + j;
-    const int tile = st / R.ST, qs = st - tile * R.ST;
-    const Group gr = R.groups[((long long)m * 2 + p) * R.ntiles + tile];
+    const Group gr = R.groups[((long long)m * 2 + p) * R.S + st];
     cd av = mk(0, 0), ap = mk(0, 0);
-    const long long stride = (long long)R.ST * 2 * mi.L;
+    const long long stride = (long long)gr.st * 2 * mi.L;
     for (int r = 0; r < gr.nr; ++r) {
-        const long long o = gr.part_off + r * stride + (long long)(qs * 2) * mi.L + j;
+        const long long o = gr.part_off + r * stride + j;
         av = cadd(av, ld2(R.part, o));
         ap = cadd(ap, ld2(R.part, o + mi.L));
     }
@@ -767,12 +1023,10 @@ __global__ void k_fsphere_step(const double2* __restrict__ in, double2* __restri
 // LDS of one workgroup: the staged positions of the largest chain group.
 // The batched form runs kWaves waves per workgroup (sharing the staged data of
 // an item); the per-term form (ACC) one wave per chain.
-template <int SE, bool ACC, int KIND>
-hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, int* counter, hipStream_t s) {
+template <int SE, bool ACC, int KIND, int R>
+hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int* counter, hipStream_t s) {
     constexpr int W = ACC ? 1 : kWaves;
-    constexpr int PS = (KIND == kMoveRow) ? 16 : (KIND == kMovePair) ? 32 : 64;  // LDS slots per chunk
-    (void)pmax;
-    const size_t lds = sizeof(double) * kStage * (size_t)(PS * SE);
+    const size_t lds = sizeof(double) * (size_t)SolveLds<SE, KIND, W, R>::kDoubles;
     int grid = nitems;
     if (counter) {
         // resident workgroups of this kernel on the whole device
@@ -780,39 +1034,62 @@ hipError_t launch_solve_t(const SolveArgs& a, int item0, int nitems, int pmax, i
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<SE, ACC, KIND, W>, 64 * W, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve<SE, ACC, KIND, W, R>, 64 * W, lds);
         if (e != hipSuccess) return e;
         grid = std::max(1, std::min(nitems, std::max(1, per_cu) * ncu));
     }
-    hipLaunchKernelGGL((k_solve<SE, ACC, KIND, W>), dim3(grid), dim3(64 * W), lds, s, a, item0, nitems, counter);
+    hipLaunchKernelGGL((k_solve<SE, ACC, KIND, W, R>), dim3(grid), dim3(64 * W), lds, s, a, item0, nitems, counter);
     return hipGetLastError();
 }
 
-// Compiled tilings: (elements per lane, move kind).  The per-term form needs
-// only those of the default policy.
-constexpr int kVariants[][2] = {{4, kMoveRow},  {6, kMoveRow},  {8, kMoveRow},  {10, kMoveRow},
-                                {12, kMoveRow}, {14, kMoveRow}, {16, kMoveRow}, {4, kMovePair},
-                                {8, kMovePair}, {16, kMoveBperm}};
-constexpr int kPerTermVariants[][2] = {{8, kMoveRow}, {8, kMovePair}, {16, kMoveBperm}};
+// Compiled variants: (elements per lane, move kind, states per item).  States
+// share a pole's factorisation when a wave holds at least that many chain
+// groups (row and row-pair tilings).  The per-term form needs only the
+// tilings of the default policy, one state per item.
+constexpr int kVariants[][3] = {
+    {4, kMoveRow, 1},  {6, kMoveRow, 1},  {8, kMoveRow, 1},  {10, kMoveRow, 1}, {12, kMoveRow, 1},
+    {14, kMoveRow, 1}, {16, kMoveRow, 1}, {4, kMovePair, 1}, {8, kMovePair, 1}, {16, kMoveBperm, 1},
+    {4, kMoveRow, 2},  {6, kMoveRow, 2},  {8, kMoveRow, 2},  {10, kMoveRow, 2}, {12, kMoveRow, 2},
+    {14, kMoveRow, 2}, {16, kMoveRow, 2}, {4, kMovePair, 2}, {8, kMovePair, 2},
+    {4, kMoveRow, 4},  {6, kMoveRow, 4},  {8, kMoveRow, 4},  {10, kMoveRow, 4}, {12, kMoveRow, 4},
+    {14, kMoveRow, 4}, {16, kMoveRow, 4}};
+constexpr int kPerTermVariants[][3] = {{8, kMoveRow, 1}, {8, kMovePair, 1}, {16, kMoveBperm, 1}};
 
 template <bool ACC>
 hipError_t launch_solve(const Launch& L, const SolveArgs& a, int* counter, hipStream_t s) {
     if (L.nitems <= 0) return hipSuccess;
     const int pcap = L.kind == kMoveRow ? 16 : L.kind == kMovePair ? 32 : 64;
     if (L.pmax > pcap) return hipErrorInvalidValue;
-#define REXI_CASE(SE_, K_) \
-    if (L.SE == SE_ && L.kind == K_) return launch_solve_t<SE_, ACC, K_>(a, L.item0, L.nitems, L.pmax, counter, s)
-    REXI_CASE(8, kMoveRow);
-    REXI_CASE(8, kMovePair);
-    REXI_CASE(16, kMoveBperm);
+    if (L.rot < 1 || L.pmax * L.rot > 64) return hipErrorInvalidValue;  // a wave holds R groups or more
+#define REXI_CASE(SE_, K_, R_) \
+    if (L.SE == SE_ && L.kind == K_ && L.rot == R_) return launch_solve_t<SE_, ACC, K_, R_>(a, L.item0, L.nitems, counter, s)
+    REXI_CASE(8, kMoveRow, 1);
+    REXI_CASE(8, kMovePair, 1);
+    REXI_CASE(16, kMoveBperm, 1);
     if constexpr (!ACC) {
-        REXI_CASE(4, kMoveRow);
-        REXI_CASE(6, kMoveRow);
-        REXI_CASE(10, kMoveRow);
-        REXI_CASE(12, kMoveRow);
-        REXI_CASE(14, kMoveRow);
-        REXI_CASE(16, kMoveRow);
-        REXI_CASE(4, kMovePair);
+        REXI_CASE(4, kMoveRow, 1);
+        REXI_CASE(6, kMoveRow, 1);
+        REXI_CASE(10, kMoveRow, 1);
+        REXI_CASE(12, kMoveRow, 1);
+        REXI_CASE(14, kMoveRow, 1);
+        REXI_CASE(16, kMoveRow, 1);
+        REXI_CASE(4, kMovePair, 1);
+        REXI_CASE(4, kMoveRow, 2);
+        REXI_CASE(6, kMoveRow, 2);
+        REXI_CASE(8, kMoveRow, 2);
+        REXI_CASE(10, kMoveRow, 2);
+        REXI_CASE(12, kMoveRow, 2);
+        REXI_CASE(14, kMoveRow, 2);
+        REXI_CASE(16, kMoveRow, 2);
+        REXI_CASE(4, kMovePair, 2);
+        REXI_CASE(8, kMovePair, 2);
+        REXI_CASE(4, kMoveRow, 4);
+        REXI_CASE(6, kMoveRow, 4);
+        REXI_CASE(8, kMoveRow, 4);
+        REXI_CASE(10, kMoveRow, 4);
+        REXI_CASE(12, kMoveRow, 4);
+        REXI_CASE(14, kMoveRow, 4);
+        REXI_CASE(16, kMoveRow, 4);
     }
 #undef REXI_CASE
     return hipErrorInvalidValue;
@@ -820,32 +1097,32 @@ hipError_t launch_solve(const Launch& L, const SolveArgs& a, int* counter, hipSt
 
 }  // namespace
 
-bool solve_variant_supported(int SE, int kind, bool per_term) {
+bool solve_variant_supported(int SE, int kind, int rot, bool per_term) {
     if (per_term) {
         for (const auto& v : kPerTermVariants)
-            if (v[0] == SE && v[1] == kind) return true;
+            if (v[0] == SE && v[1] == kind && v[2] == rot) return true;
         return false;
     }
     for (const auto& v : kVariants)
-        if (v[0] == SE && v[1] == kind) return true;
+        if (v[0] == SE && v[1] == kind && v[2] == rot) return true;
     return false;
 }
 int solve_waves_per_item() { return kWaves; }
 
 int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap) {
     int n = 0;
-    auto put = [&](int a, int b) {
+    auto put = [&](int a, int b, int c) {
         if (n < cap) {
             if (se) se[n] = a;
             if (kind) kind[n] = b;
-            if (st) st[n] = 1;
+            if (st) st[n] = c;
         }
         ++n;
     };
     if (per_term) {
-        for (const auto& v : kPerTermVariants) put(v[0], v[1]);
+        for (const auto& v : kPerTermVariants) put(v[0], v[1], v[2]);
     } else {
-        for (const auto& v : kVariants) put(v[0], v[1]);
+        for (const auto& v : kVariants) put(v[0], v[1], v[2]);
     }
     return n;
 }
@@ -918,8 +1195,6 @@ hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part
     r.ch_var_out = u_out ? nullptr : pl->d_ch_var[buf_out];
     r.ch_phi_out = u_out ? nullptr : pl->d_ch_phi[buf_out];
     r.u_out = (double2*)u_out;
-    r.ST = sc.ST;
-    r.ntiles = (S + sc.ST - 1) / sc.ST;
     r.S = S;
     r.invert_scale = adjoint;
     r.nspec = pl->nspec;

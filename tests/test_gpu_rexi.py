@@ -88,11 +88,12 @@ def _every_schedule(plan, S, u0, want, want_a, T, tag, torch_dev):
         _VARIANTS_SEEN.update(classes)
 
 
-@pytest.mark.parametrize("T,S,M,dt", [(160, 2, 32, 600.0), (255, 1, 24, 300.0), (255, 4, 24, 300.0)])
+@pytest.mark.parametrize("T,S,M,dt", [(160, 2, 32, 600.0), (255, 2, 24, 300.0), (255, 4, 24, 300.0)])
 def test_step_long_chains_every_schedule(torch_dev, T, S, M, dt):
     # chains of up to 255 elements: 32-lane groups over row pairs and every
-    # row tiling from 4 to 16 elements per lane, for every policy, both
-    # directions, every order
+    # row tiling from 4 to 16 elements per lane, for every policy, with one
+    # state per work item and with 2 or 4 states sharing each factorisation,
+    # both directions, every order
     w = synth.Workload("long", T=T, nlat=0, nlon=0, dt=dt, M=M, states=S)
     u0 = synth.random_state(T, S, 200 + T)
     want = oracle_run_parallel(u0, w)
@@ -121,7 +122,7 @@ def test_every_batched_variant_checked():
     # every compiled variant of the batched solve was launched by one of the
     # every-schedule tests above and checked there on every order
     import paper_1812_03431_amd as rexi
-    need = {"long160_2", "long255_1", "long255_4", "vlong400"}
+    need = {"long160_2", "long255_2", "long255_4", "vlong400"}
     if not need <= _CONTRIBUTORS:
         pytest.skip("needs the every-schedule tests of this module to have run and passed first")
     missing = set(rexi.solve_variants()) - _VARIANTS_SEEN
@@ -331,19 +332,22 @@ def test_graph_replays_match_direct_launches(torch_dev):
 
 
 def test_persistent_and_regular_schedules_agree(torch_dev):
+    # candidates come in blocks of 36 (one per states-per-item mode), each
+    # 18 regular then 18 persistent: the same two policies both ways agree
     w = synth.WORKLOADS["t128_batched"]
     plan = _plan(w, grid=False)
     u0 = _gpu(synth.random_state(w.T, w.states, 0), torch_dev)
     n = plan.schedule_count(w.states)
-    assert n % 2 == 0
+    assert n % 36 == 0
     ref = None
-    for i in (0, 2, n // 2, n // 2 + 2):    # regular and persistent variants of two policies
-        plan.set_schedule(w.states, i)
-        got = plan.step(u0).cpu().numpy()
-        if ref is None:
-            ref = got
-        else:
-            assert rel_err(got, ref) < 1e-13
+    for base in range(0, n, 36):
+        for i in (base, base + 2, base + 18, base + 20):
+            plan.set_schedule(w.states, i)
+            got = plan.step(u0).cpu().numpy()
+            if ref is None:
+                ref = got
+            else:
+                assert rel_err(got, ref) < 1e-13, i
 
 
 def test_concurrent_and_serial_class_launches_agree(torch_dev):
