@@ -39,13 +39,20 @@ HBM_PEAK = 8000.0           # GB/s
 
 
 def solve_flops_per_launch(N, T, S):
-    """Algorithmic FP64 flops of one REXI step of S states (Thomas count).
+    """Algorithmic FP64 flops of one forward REXI step of S states, as the
+    measurement contract counts them: nspec N (40 + 156 S), i.e. per pole and
+    per (n, m) 40 flops of factorisation and 156 per state (both signs' right-
+    hand sides, Phi elimination, sweeps and the weighted accumulation)."""
+    nspec = (T + 1) * (T + 2) // 2
+    return float(nspec) * N * (40 + 156 * S)
 
-    Per pole and per (n, m) with (n, m) != (0, 0), both parity chains hold one
-    element each: factorisation 2 x 16 flops (diagonal, pivot update, complex
-    reciprocal, multiplier) and, per right-hand side (2 per state), 2 x 34
-    flops (Phi elimination, forward sweep, back substitution, weighted
-    accumulation of the chain variable and of Phi)."""
+
+def solve_flops_thomas(N, T, S):
+    """The same step by a plain Thomas count: per pole and per (n, m) !=
+    (0, 0), both parity chains hold one element each; factorisation 2 x 16
+    flops (diagonal, pivot update, complex reciprocal, multiplier) and per
+    right-hand side (2 per state) 2 x 34 flops (Phi elimination, forward
+    sweep, back substitution, weighted accumulation)."""
     nspec = (T + 1) * (T + 2) // 2
     return float(N) * (nspec - 1) * (32 + 136 * S)
 
@@ -97,10 +104,10 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(digest):
-    """HBM bytes per solve launch from the committed counter summary, if it was
-    taken on the current kernel source; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "k_solve_t256_fwd_adj_traffic.json")
+def load_summary(name, digest):
+    """A committed counter summary from profiles/, if it was taken on the
+    current solve kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             d = json.load(f)
@@ -108,7 +115,7 @@ def load_traffic(digest):
         return None
     if d.get("kernel_source_sha256_16") != digest:
         return None
-    return d.get("traffic_bytes_per_launch")
+    return d
 
 
 def cpu_baseline(w, budget_s, gpu_fwd=None, gpu_adj=None):
@@ -124,6 +131,10 @@ def cpu_baseline(w, budget_s, gpu_fwd=None, gpu_adj=None):
     u0 = synth.random_state(w.T, w.states, 0)
     stride = 8  # 33 of 257 orders at T256, about 15 s of oracle time on one core
     orders = list(range(0, w.T + 1, stride))
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
     t0, c0 = time.perf_counter(), time.process_time()
     done = []
     fwd = np.zeros_like(u0)
@@ -138,6 +149,9 @@ def cpu_baseline(w, budget_s, gpu_fwd=None, gpu_adj=None):
     cpu = time.process_time() - c0
     blocks = 2 * N * len(done)
     out = {"value": blocks / wall, "unit": "blocks/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
+           "cpu_count": os.cpu_count(), "cpus_allowed": affinity,
+           "cores_note": "cores = CPU time / wall time of the sample (threads actually used); cpu_count = "
+                         "os.cpu_count() of the host",
            "sample": f"one forward and one adjoint step of {w.states} states for orders m = "
                      f"{done[0]}..{done[-1]} step {stride} ({len(done)} of {w.T + 1} orders, mean chain "
                      f"length {np.mean([w.T + 1 - m for m in done]):.0f}); {wall:.1f} s wall"}
@@ -148,11 +162,28 @@ def cpu_baseline(w, budget_s, gpu_fwd=None, gpu_adj=None):
             mask[o:o + w.T + 1 - m] = True
 
         def worst(got, want):
-            return max(float(np.linalg.norm(got[s, v, mask] - want[s, v, mask]) / np.linalg.norm(want[s, v, mask]))
-                       for s in range(u0.shape[0]) for v in range(3))
+            var = max(float(np.linalg.norm(got[s, v, mask] - want[s, v, mask]) / np.linalg.norm(want[s, v, mask]))
+                      for s in range(u0.shape[0]) for v in range(3))
+            blk = 0.0
+            for s in range(u0.shape[0]):
+                for v in range(3):
+                    for m in done:
+                        o = m * (w.T + 1) - m * (m - 1) // 2
+                        sl = slice(o, o + w.T + 1 - m)
+                        d = np.linalg.norm(want[s, v, sl])
+                        if d > 0:
+                            blk = max(blk, float(np.linalg.norm(got[s, v, sl] - want[s, v, sl]) / d))
+            return var, blk
+        fv, fb = worst(gpu_fwd, fwd)
+        av, ab = worst(gpu_adj, adj)
+        ok = max(fv, fb, av, ab) <= 1e-10
         out["gpu_parity"] = {"orders": f"{done[0]}..{done[-1]} step {stride}",
-                             "max_rel_l2_forward": worst(gpu_fwd, fwd), "max_rel_l2_adjoint": worst(gpu_adj, adj),
-                             "per": "state and variable", "bound": 1e-10}
+                             "max_rel_l2_forward": fv, "max_rel_l2_adjoint": av,
+                             "max_block_rel_l2_forward": fb, "max_block_rel_l2_adjoint": ab,
+                             "per": "state and variable over the sampled orders, and within each order's block",
+                             "bound": 1e-10, "ok": ok}
+        if not ok:
+            print(f"bench.py: GPU step differs from the oracle beyond 1e-10: {out['gpu_parity']}", file=sys.stderr)
     return out
 
 
@@ -251,6 +282,11 @@ def dispersion_run(rexi, synth, torch, dev):
             "max_abs_growth_per_s": res["max_abs_growth"], "seconds": time.perf_counter() - t0}
 
 
+def stage(msg):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +325,7 @@ def main():
 
     grid = torch.from_numpy(synth.random_grid(w.nlat, w.nlon, B, 0)).to(dev)
     target = torch.from_numpy(synth.random_state(T, S, 100)[:, 0].copy()).to(dev)
+    stage("plan built")
     if args.schedule >= 0:
         plan.set_schedule(S, args.schedule)
         chosen = args.schedule
@@ -310,9 +347,14 @@ def main():
             g = plan.step_adjoint(g, ck)
         return plan.sh_inverse(g.view(B, plan.nspec))
 
+    stage(f"schedule {chosen}; warm-up")
     for _ in range(args.warmup):
         job()
     torch.cuda.synchronize()
+    # the timed region runs the product path (captured step graphs); the plan
+    # brackets each step's graph replay and each Legendre launch with a HIP
+    # event pair on the launch stream
+    plan.set_graphs(True)
     plan.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -329,6 +371,7 @@ def main():
     blocks_per_job = 2 * w.steps * N * (T + 1)
     value = blocks_per_job * args.steps / elapsed
 
+    stage(f"timed {args.steps} steps: {elapsed / args.steps * 1e3:.2f} ms each")
     # the plain per-term launch form vs the batched form, one forward step each
     u = plan.sh_forward(grid).view(S, 3, plan.nspec)
     plan.step(u, 1)
@@ -347,8 +390,20 @@ def main():
     avg_solve_s = solve_ms / 1e3 / max(1, solve_n)
     fl = solve_flops_per_launch(N, T, S)
     achieved = fl / avg_solve_s / 1e12
+    fl_thomas = solve_flops_thomas(N, T, S)
     digest = kernel_source_digest()
-    traffic = load_traffic(digest)
+    tr = load_summary("k_solve_t256_fwd_adj_traffic.json", digest)
+    traffic = tr.get("traffic_bytes_per_launch") if tr else None
+    state_bytes = 2.0 * S * 3 * plan.nspec * 16       # state in and out of one step
+    ctr = load_summary("k_solve_t256_fwd_adj_counters.json", digest)
+    pt = load_summary("per_term_t256_traffic.json", digest)
+    per_term_hbm = None
+    if pt:
+        b_step = pt["bytes_per_step"]
+        per_term_hbm = {"bytes_per_step": b_step, "achieved_GBps": b_step / (per_term_ms / 1e3) / 1e9,
+                        "peak_GBps": HBM_PEAK, "frac": b_step / (per_term_ms / 1e3) / 1e9 / HBM_PEAK,
+                        "source": "profiles/per_term_t256_traffic.json (FETCH_SIZE + WRITE_SIZE of one "
+                                  "per-term step, scaled by a copy kernel's reading); time: this run"}
     lflops = legendre_flops(T, w.nlat, B)
     leg = {}
     if lf_n and li_n:
@@ -378,6 +433,7 @@ def main():
                    "h": w.h, "poles": N, "states": S, "forward_steps": w.steps, "adjoint_steps": w.steps,
                    "checkpoint_every": ck, "sh_fields": B, "blocks_per_step": blocks_per_job},
         "schedule": chosen,
+        "timed_path": "step graphs on; HIP events around each step graph and Legendre launch",
         "rexi_step_ms": avg_solve_s * 1e3,
         "fwd_plus_adjoint_step_ms": 2 * avg_solve_s * 1e3,
         "batched_step_ms": batched_ms,
@@ -385,8 +441,17 @@ def main():
         "batched_vs_per_term": per_term_ms / batched_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK, "traffic": traffic, "kernel": "k_solve",
-                     "flops_per_launch": fl, "avg_launch_ms": avg_solve_s * 1e3, "launches": solve_n,
+                     "flops_per_launch": fl, "flop_count": "nspec N (40 + 156 S) per forward step",
+                     "avg_launch_ms": avg_solve_s * 1e3, "launches": solve_n,
+                     "launch": "one step: the captured graph of the solve class launches and the reduction",
+                     "thomas_flops_per_launch": fl_thomas, "thomas_achieved": fl_thomas / avg_solve_s / 1e12,
+                     "thomas_frac": fl_thomas / avg_solve_s / 1e12 / FP64_VECTOR_PEAK,
+                     "algorithmic_bytes_per_launch": state_bytes,
+                     "algorithmic_GBps": state_bytes / avg_solve_s / 1e9,
+                     "traffic_GBps": (traffic / avg_solve_s / 1e9) if traffic else None,
+                     "executed_fp64_flops_per_launch": ctr.get("executed_fp64_flops_per_step") if ctr else None,
                      "kernel_source_sha256_16": digest},
+        "per_term_hbm": per_term_hbm,
         "legendre": leg,
     }
     if args.copy_calibration:
@@ -399,6 +464,7 @@ def main():
         torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 1 << 30
+    stage("per-term form and extras")
     if not args.no_bumps:
         rec["bumps"] = bump_runs(rexi, synth, torch, dev)
         rec["dispersion"] = dispersion_run(rexi, synth, torch, dev)
@@ -416,6 +482,7 @@ def main():
                            "quantity": "(1/4) sum c_m [Phibar a^2/(n(n+1)) (|zeta|^2+|delta|^2) + |Phi|^2] "
                                        "of the 4 benchmark states"}
     if not args.no_cpu_baseline:
+        stage("oracle on the host")
         us = torch.from_numpy(synth.random_state(T, S, 0)).to(dev)
         gf = plan.step(us).cpu().numpy()
         ga = plan.step_adjoint(us).cpu().numpy()

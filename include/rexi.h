@@ -246,10 +246,12 @@ int rexi_plan_set_streams(rexi_plan *plan, int enable);
 
 /* Kernel timing for measurement.  rexi_plan_set_timing(plan, 1) makes the plan
  * bracket every later launch of the timed kernels with a HIP event pair on the
- * launch stream (steps then run as individual launches, not graphs); 0 stops
- * recording.  rexi_plan_kernel_time synchronises on the
- * recorded events and returns the summed elapsed time (ms) and the number of
- * launches of one kernel since the last query, then forgets them.
+ * launch stream; 0 stops recording.  A solve timing covers one step: with step
+ * graphs on (the default) the replay of the step's graph, i.e. the solve
+ * launches and the reduction of their partial sums; with graphs off the solve
+ * launches alone.  rexi_plan_kernel_time synchronises on the recorded events
+ * and returns the summed elapsed time (ms) and the number of launches of one
+ * kernel since the last query, then forgets them.
  *   kernel  REXI_KERNEL_SOLVE (fused banded solve), REXI_KERNEL_LEGENDRE_FWD,
  *           REXI_KERNEL_LEGENDRE_INV */
 enum { REXI_KERNEL_SOLVE = 0, REXI_KERNEL_LEGENDRE_FWD = 1, REXI_KERNEL_LEGENDRE_INV = 2 };

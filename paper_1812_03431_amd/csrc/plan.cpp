@@ -414,13 +414,16 @@ int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S
     }
     REXI_HIP(enqueue_prep(pl, u0, 0, S, adjoint, pl->sched_layout, s));
     int cur = 0;
-    if (pl->use_graphs && !pl->timing) {
-        // captured step graphs (solve + reduction), then the final layout change
+    if (pl->use_graphs) {
+        // captured step graphs (solve + reduction), then the final layout
+        // change; with timing on, each replay is bracketed by an event pair
         for (int k = 0; k < nsteps; ++k) {
             hipGraphExec_t exec = nullptr;
             int rc = step_graph(pl, sc, S, adjoint, cur, &exec);
             if (rc) return rc;
+            REXI_HIP(timed_begin(pl, REXI_KERNEL_SOLVE, s));
             REXI_HIP(hipGraphLaunch(exec, s));
+            REXI_HIP(timed_end(pl, REXI_KERNEL_SOLVE, s));
             cur ^= 1;
         }
         REXI_HIP(enqueue_finish(pl, cur, u1, S, adjoint, pl->sched_layout, s));

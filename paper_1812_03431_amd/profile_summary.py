@@ -1,0 +1,218 @@
+"""Summaries of rocprofv3 counter runs of the benchmark, for profiles/.
+
+traffic:  two runs of ``bench.py --copy-calibration`` under ``rocprofv3 --pmc
+          FETCH_SIZE`` and ``--pmc WRITE_SIZE`` -> HBM bytes of one REXI step
+          (the fused solve's class launches and the reduction; mean per class
+          over all steps of the run) and of one per-term step (the sum over
+          its per-pole launches; the benchmark runs one).  Each counter is
+          scaled by what it reads for an elementwise kernel that reads and
+          writes 1 GiB (torch.mul on 2^27 doubles; the largest such
+          dispatch of the run).
+counters: one run under ``rocprofv3 --pmc`` with SQ counters -> per class and
+          per step: VALU wave-instructions, FP64 flops executed
+          (SQ_INSTS_VALU_FLOPS_FP64 counts the flops of one lane per
+          wave-instruction, so a step executes 64 times its sum), and the
+          other counters given.
+
+Writes JSON keyed by the solve kernel source's hash (bench.py reports a
+summary only while the hash matches the source).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SOLVE = re.compile(r"k_solve<(\d+), (true|false), (\d), (\d), (\d)>")
+
+
+def source_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1812_03431_amd", "csrc", "rexi_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def rows(path):
+    with open(path) as f:
+        yield from csv.DictReader(f)
+
+
+def per_dispatch(path, counter):
+    """{dispatch id: (kernel name, value summed over the counter's instances)}"""
+    out = {}
+    for r in rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        name, v = out.get(d, (r["Kernel_Name"], 0.0))
+        out[d] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def class_of(name):
+    m = SOLVE.search(name)
+    if m:
+        se, pt, kind, w, rot = m.groups()
+        return ("per_term" if pt == "true" else "batched", f"k_solve<{se}, {pt}, {kind}, {w}, {rot}>")
+    if "k_reduce" in name:
+        return ("batched", "k_reduce")
+    return (None, None)
+
+
+def calibration(path, counter):
+    """The counter's reading for the 1 GiB elementwise kernel: the largest
+    reading among the run's torch multiply dispatches (the others are small
+    tensors)."""
+    vals = [v for d, (n, v) in per_dispatch(path, counter).items() if "MulFunctor" in n]
+    if not vals:
+        raise SystemExit(f"{path}: no calibration dispatch (run bench.py with --copy-calibration)")
+    return max(vals)
+
+
+def traffic(fetch_csv, write_csv, schedule, workload, commands):
+    GiB_KiB = float(1 << 20)
+    fcal, wcal = calibration(fetch_csv, "FETCH_SIZE"), calibration(write_csv, "WRITE_SIZE")
+    fscale, wscale = GiB_KiB / fcal, GiB_KiB / wcal
+    out = {}
+    for kind in ("batched", "per_term"):
+        cls = collections.defaultdict(lambda: {"fetch_kib": [], "write_kib": []})
+        for path, counter, key in ((fetch_csv, "FETCH_SIZE", "fetch_kib"), (write_csv, "WRITE_SIZE", "write_kib")):
+            for d, (name, v) in per_dispatch(path, counter).items():
+                k, c = class_of(name)
+                if k == kind:
+                    cls[c][key].append(v)
+        out[kind] = cls
+    per_class = {}
+    step = 0.0
+    for c, v in out["batched"].items():
+        f = sum(v["fetch_kib"]) / max(1, len(v["fetch_kib"]))
+        w = sum(v["write_kib"]) / max(1, len(v["write_kib"]))
+        per_class[c] = {"fetch_kib_mean": f, "write_kib_mean": w, "dispatches": len(v["fetch_kib"])}
+        step += (f * fscale + w * wscale) * 1024.0
+    pt_f = sum(sum(v["fetch_kib"]) for v in out["per_term"].values())
+    pt_w = sum(sum(v["write_kib"]) for v in out["per_term"].values())
+    pt_n = sum(len(v["fetch_kib"]) for v in out["per_term"].values())
+    digest = source_digest()
+    cal = {"kernel": "torch.mul(a, 1.0, out=b) on 2^27 doubles: reads 1 GiB, writes 1 GiB",
+           "fetch_kib": fcal, "write_kib": wcal, "fetch_scale": fscale, "write_scale": wscale,
+           "dispatch": "the largest reading among the run's torch multiply dispatches"}
+    solve = {"kernel": "k_solve (fused REXI solve) class launches and k_reduce of one step",
+             "workload": workload, "schedule": schedule, "kernel_source_sha256_16": digest,
+             "commands": commands, "calibration": cal, "per_class": per_class,
+             "traffic_bytes_per_launch": step,
+             "note": "one launch = one step; bytes = sum over the step's kernels of the mean per dispatch of "
+                     "FETCH_SIZE*fetch_scale + WRITE_SIZE*write_scale (KiB -> bytes)"}
+    per_term = {"kernel": "k_solve per-term launches (one per pole and class) of one per-term step",
+                "workload": workload, "kernel_source_sha256_16": digest, "commands": commands,
+                "calibration": cal, "dispatches": pt_n, "fetch_kib_total": pt_f, "write_kib_total": pt_w,
+                "bytes_per_step": (pt_f * fscale + pt_w * wscale) * 1024.0}
+    return solve, per_term
+
+
+def counters(csv_path, schedule, workload, commands, steps_note):
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows(csv_path):
+        k, c = class_of(r["Kernel_Name"])
+        if k != "batched":
+            continue
+        per[c][(r["Counter_Name"], r["Dispatch_Id"])].append(float(r["Counter_Value"]))
+    per_class = {}
+    step = collections.Counter()
+    for c, d in per.items():
+        acc = collections.defaultdict(list)
+        for (name, _), v in d.items():
+            acc[name].append(sum(v))
+        mean = {name: sum(v) / len(v) for name, v in acc.items()}
+        mean["dispatches"] = max(len(v) for v in acc.values())
+        per_class[c] = mean
+        for name, v in mean.items():
+            if name != "dispatches":
+                step[name] += v
+    out = {"kernel": "k_solve class launches and k_reduce of one step", "workload": workload,
+           "schedule": schedule, "kernel_source_sha256_16": source_digest(), "commands": commands,
+           "per_class_mean_per_dispatch": per_class, "per_step": dict(step), "note": steps_note}
+    if "SQ_INSTS_VALU_FLOPS_FP64" in step:
+        out["executed_fp64_flops_per_step"] = 64.0 * step["SQ_INSTS_VALU_FLOPS_FP64"]
+    return out
+
+
+def stats(stats_csv, trace_csv, schedule, workload, command, events_ms):
+    """Text summary of a kernel-trace run: per-kernel statistics and the span
+    of each REXI step (first solve class start to its reduction's end)."""
+    lines = [f"# rocprofv3 kernel statistics: {workload} benchmark job (bench.py), schedule {schedule}",
+             "# command (on the GPU box, from /tmp with TMPDIR=/tmp):", f"#   {command}",
+             "# one REXI step = one captured graph: a k_solve launch per tile class "
+             "(template <elements per lane, per-term, move kind, waves, states per item>) and k_reduce;",
+             "# k_solve<.., true, .., 1, 1> are the per-term comparison launches (one per pole and class).",
+             f"# kernel source sha256[:16] = {source_digest()}"]
+    spans, start = [], None
+    for r in sorted(rows(trace_csv), key=lambda r: int(r["Start_Timestamp"])):
+        n = r["Kernel_Name"]
+        k, c = class_of(n)
+        if k == "batched" and c != "k_reduce":
+            if start is None:
+                start = int(r["Start_Timestamp"])
+        elif c == "k_reduce" and start is not None:
+            spans.append((int(r["End_Timestamp"]) - start) / 1e3)
+            start = None
+    if spans:
+        spans.sort()
+        lines.append(f"# step span (first class start to reduction end, {len(spans)} steps): mean "
+                     f"{sum(spans) / len(spans):.1f} us, median {spans[len(spans) // 2]:.1f} us"
+                     + (f"; HIP events around the step graphs in the bench line: {events_ms * 1e3:.1f} us"
+                        if events_ms else ""))
+    lines.append("# (class launches overlap on side streams, so per-class durations below do not add up to a step)")
+    lines.append("")
+    lines.append(" calls   total_ms     avg_us    min_us    max_us    pct  kernel")
+    for r in sorted(rows(stats_csv), key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}  {r['Name'][:150]}")
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="what", required=True)
+    k = sub.add_parser("stats")
+    k.add_argument("--stats", required=True)
+    k.add_argument("--trace", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--events-ms", type=float, default=None, help="the bench line's HIP-event step time (ms)")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--out-solve", required=True)
+    t.add_argument("--out-per-term", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--out", required=True)
+    for p in (t, c, k):
+        p.add_argument("--schedule", type=int, required=True)
+        p.add_argument("--workload", default="t256_fwd_adj")
+        p.add_argument("--command", action="append", default=[], help="the rocprofv3 command lines (recorded)")
+    a = ap.parse_args()
+    if a.what == "stats":
+        with open(a.out, "w") as f:
+            f.write(stats(a.stats, a.trace, a.schedule, a.workload, " ".join(a.command), a.events_ms))
+    elif a.what == "traffic":
+        solve, per_term = traffic(a.fetch, a.write, a.schedule, a.workload, a.command)
+        with open(a.out_solve, "w") as f:
+            json.dump(solve, f, indent=1)
+        with open(a.out_per_term, "w") as f:
+            json.dump(per_term, f, indent=1)
+    else:
+        out = counters(a.csv, a.schedule, a.workload, a.command,
+                       "per step = sum over the step's kernels of the mean per dispatch")
+        with open(a.out, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
