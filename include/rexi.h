@@ -192,6 +192,25 @@ int rexi_step(rexi_plan *plan, const void *u0, void *u1, int S, int nsteps, void
  * Arguments as rexi_step. */
 int rexi_step_adjoint(rexi_plan *plan, const void *g1, void *g0, int S, int nsteps, void *stream);
 
+/* rexi_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and the plan's current schedule for S, with the workspace
+ * (states in chain layout, partial sums, work counters) in one fixed 64 MiB
+ * device array of the library instead of the plan's allocations; kernels
+ * launched one by one, no graph, no event.  Calls no hipMalloc, hipFree or
+ * other allocating routine.
+ *   Arguments as rexi_step.  The schedules for S must exist: one earlier
+ *   rexi_step, rexi_plan_set_schedule or rexi_plan_autotune call with S
+ *   builds them (and allocates); otherwise REXI_EINVAL.  A step whose
+ *   workspace exceeds 64 MiB returns REXI_EUNSUPPORTED (a schedule with fewer
+ *   work items, rexi_plan_set_schedule, needs less; T256 with 4 states fits
+ *   with about 2048 items).  Persistent schedules (a resident grid taking
+ *   items from a counter) return REXI_EUNSUPPORTED.
+ *   The array is per GPU and lives until the process ends; every call on a
+ *   GPU uses it, so calls that overlap on one GPU (on different streams or
+ *   from different threads) race. */
+int rexi_step_noalloc(rexi_plan *plan, const void *u0, void *u1, int S, int nsteps, void *stream);
+
 /* One forward step in the plain per-term form: one launch per pole k that
  * solves every m-block of (alpha_k +- dt L) and accumulates into a device
  * accumulator, then a final conversion.  Same arithmetic and result as

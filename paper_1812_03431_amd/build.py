@@ -19,6 +19,8 @@ FLAGS = [
     # instead of copying through AGPRs (and waiting for each MFMA) every k-step
     "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
+    # every symbol the library uses must be defined in it or its dependencies
+    "-Wl,--no-undefined",
 ]
 
 

@@ -105,6 +105,17 @@ struct Launch {
 
 constexpr int kMaxLaunches = 8;  // solve launches per step (tile classes)
 
+// Device workspace of a step: the states in chain layout (double buffered
+// between steps), the solve's partial sums and the work counters of
+// persistent launches.  A plan owns one; the no-allocation step carves one
+// out of a fixed device array.
+struct Workspace {
+    double2* ch_var[2];  // [S][nslots + 2]
+    double2* ch_phi[2];  // [S][nspec]
+    double2* part;       // partial sums, the schedule's part_size entries
+    int* counters;       // kMaxLaunches
+};
+
 struct Schedule {
     bool persistent = false;  // resident grid + atomic work counter per launch
     int SM = 4;       // largest elements-per-lane class used
@@ -191,12 +202,49 @@ struct rexi_plan {
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[rexi::kMaxLaunches] = {};
 
+    // the device the plan was created on, and the no-allocation step's fixed
+    // workspace there (see rexi_step_noalloc)
+    int device = 0;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+
     // measurement: event pairs around timed launches, per kernel kind
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events[3];
 };
 
 namespace rexi {
+// Launchers (rexi_kernels.hip, sh_kernels.hip) and library internals used
+// across the sources.
+bool solve_variant_supported(int SE, int kind, int rot, bool per_term);
+int solve_waves_per_item();
+int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap);
+hipError_t enqueue_prep(rexi_plan* pl, const Workspace& ws, const void* u, int buf, int S, int adjoint,
+                        const MInfo* d_layout, hipStream_t s);
+hipError_t enqueue_solve(rexi_plan* pl, const Workspace& ws, const Schedule& sc, int buf, int S, int adjoint,
+                         hipStream_t s);
+hipError_t enqueue_reduce(rexi_plan* pl, const Workspace& ws, const Schedule& sc, const double2* part, int buf_in,
+                          int buf_out, void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s);
+hipError_t enqueue_zero(double2* p, long long n, hipStream_t s);
+hipError_t enqueue_fsphere_step(rexi_plan* pl, const void* in, void* out, int S, int adjoint, hipStream_t s);
+hipError_t enqueue_finish(rexi_plan* pl, const Workspace& ws, int buf, void* u, int S, int adjoint,
+                          const MInfo* d_layout, hipStream_t s);
+hipError_t enqueue_per_term_pole(rexi_plan* pl, const Workspace& ws, const Schedule& sc, int k, int buf, int S,
+                                 hipStream_t s);
+int sh_setup(rexi_plan* pl);
+void sh_release(rexi_plan* pl);
+int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStream_t s);
+int sh_vec_run(rexi_plan* pl, const void* in, void* out, long long stride, int B, bool to_uv, hipStream_t s);
+int check_state_call(rexi_plan* pl, const void* in, const void* out, int S, int nsteps);
+// The no-allocation step's fixed device array: its address on the current
+// device, looked up once per device (noalloc.hip).
+int scratch_setup(void** ptr, size_t* bytes);
+
+// The plan's own workspace.
+inline Workspace plan_workspace(const rexi_plan* pl) {
+    return Workspace{{pl->d_ch_var[0], pl->d_ch_var[1]}, {pl->d_ch_phi[0], pl->d_ch_phi[1]}, pl->d_part,
+                     pl->d_counters};
+}
 // Record an event before / after a timed launch when timing is on.
 hipError_t timed_begin(rexi_plan* pl, int kind, hipStream_t s);
 hipError_t timed_end(rexi_plan* pl, int kind, hipStream_t s);

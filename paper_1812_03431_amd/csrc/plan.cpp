@@ -15,23 +15,6 @@
 
 namespace rexi {
 
-bool solve_variant_supported(int SE, int kind, int rot, bool per_term);
-int solve_waves_per_item();
-int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap);
-hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
-                        hipStream_t s);
-hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int adjoint, hipStream_t s);
-hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,
-                          void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s);
-hipError_t enqueue_zero(double2* p, long long n, hipStream_t s);
-hipError_t enqueue_fsphere_step(rexi_plan* pl, const void* in, void* out, int S, int adjoint, hipStream_t s);
-hipError_t enqueue_finish(rexi_plan* pl, int buf, void* u, int S, int adjoint, const MInfo* d_layout,
-                          hipStream_t s);
-hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int buf, int S, hipStream_t s);
-int sh_setup(rexi_plan* pl);
-void sh_release(rexi_plan* pl);
-int sh_run(rexi_plan* pl, const void* in, void* out, int B, bool forward, hipStream_t s);
-int sh_vec_run(rexi_plan* pl, const void* in, void* out, long long stride, int B, bool to_uv, hipStream_t s);
 
 namespace {
 thread_local std::string g_err;
@@ -367,16 +350,6 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-int check_state_call(rexi_plan* pl, const void* in, const void* out, int S, int nsteps) {
-    if (!pl) return fail(REXI_EINVAL, "plan is NULL");
-    if (!in || !out) return fail(REXI_EINVAL, "state pointer is NULL");
-    if (S < 1) return fail(REXI_EINVAL, "S must be >= 1");
-    if (S > pl->prm.max_states) return fail(REXI_EUNSUPPORTED, "S exceeds the plan's max_states");
-    if (nsteps < 0) return fail(REXI_EINVAL, "nsteps must be >= 0");
-    const size_t bytes = (size_t)S * 3 * pl->nspec * 16;
-    if (overlaps(in, bytes, out, bytes)) return fail(REXI_EALIAS, "output overlaps input");
-    return REXI_OK;
-}
 
 // The graph of one step for (S, direction, input buffer): solve launches and
 // the reduction into the other chain buffer, captured on the plan's stream.
@@ -388,10 +361,11 @@ int step_graph(rexi_plan* pl, const Schedule& sc, int S, int adjoint, int buf, h
         }
     hipGraph_t graph = nullptr;
     REXI_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = enqueue_solve(pl, sc, buf, S, adjoint, pl->cap_stream);
+    const Workspace ws = plan_workspace(pl);
+    hipError_t e1 = enqueue_solve(pl, ws, sc, buf, S, adjoint, pl->cap_stream);
     hipError_t e2 = hipSuccess;
     if (e1 == hipSuccess)
-        e2 = enqueue_reduce(pl, sc, pl->d_part, buf, buf ^ 1, nullptr, S, adjoint, pl->d_slot_m, pl->cap_stream);
+        e2 = enqueue_reduce(pl, ws, sc, ws.part, buf, buf ^ 1, nullptr, S, adjoint, pl->d_slot_m, pl->cap_stream);
     hipError_t e3 = hipStreamEndCapture(pl->cap_stream, &graph);
     if (e1 != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e1, "capture solve"); }
     if (e2 != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e2, "capture reduce"); }
@@ -412,7 +386,8 @@ int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S
         REXI_HIP(hipMemcpyAsync(u1, u0, bytes, hipMemcpyDeviceToDevice, s));
         return REXI_OK;
     }
-    REXI_HIP(enqueue_prep(pl, u0, 0, S, adjoint, pl->sched_layout, s));
+    const Workspace ws = plan_workspace(pl);
+    REXI_HIP(enqueue_prep(pl, ws, u0, 0, S, adjoint, pl->sched_layout, s));
     int cur = 0;
     if (pl->use_graphs) {
         // captured step graphs (solve + reduction), then the final layout
@@ -426,21 +401,33 @@ int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S
             REXI_HIP(timed_end(pl, REXI_KERNEL_SOLVE, s));
             cur ^= 1;
         }
-        REXI_HIP(enqueue_finish(pl, cur, u1, S, adjoint, pl->sched_layout, s));
+        REXI_HIP(enqueue_finish(pl, ws, cur, u1, S, adjoint, pl->sched_layout, s));
         return REXI_OK;
     }
     for (int k = 0; k < nsteps; ++k) {
         const bool last = (k == nsteps - 1);
         REXI_HIP(timed_begin(pl, REXI_KERNEL_SOLVE, s));
-        REXI_HIP(enqueue_solve(pl, sc, cur, S, adjoint, s));
+        REXI_HIP(enqueue_solve(pl, ws, sc, cur, S, adjoint, s));
         REXI_HIP(timed_end(pl, REXI_KERNEL_SOLVE, s));
-        REXI_HIP(enqueue_reduce(pl, sc, pl->d_part, cur, cur ^ 1, last ? u1 : nullptr, S, adjoint, pl->d_slot_m, s));
+        REXI_HIP(enqueue_reduce(pl, ws, sc, ws.part, cur, cur ^ 1, last ? u1 : nullptr, S, adjoint, pl->d_slot_m, s));
         cur ^= 1;
     }
     return REXI_OK;
 }
 
 }  // namespace
+
+int check_state_call(rexi_plan* pl, const void* in, const void* out, int S, int nsteps) {
+    if (!pl) return fail(REXI_EINVAL, "plan is NULL");
+    if (!in || !out) return fail(REXI_EINVAL, "state pointer is NULL");
+    if (S < 1) return fail(REXI_EINVAL, "S must be >= 1");
+    if (S > pl->prm.max_states) return fail(REXI_EUNSUPPORTED, "S exceeds the plan's max_states");
+    if (nsteps < 0) return fail(REXI_EINVAL, "nsteps must be >= 0");
+    const size_t bytes = (size_t)S * 3 * pl->nspec * 16;
+    if (overlaps(in, bytes, out, bytes)) return fail(REXI_EALIAS, "output overlaps input");
+    return REXI_OK;
+}
+
 }  // namespace rexi
 
 using namespace rexi;
@@ -653,6 +640,12 @@ int create(const rexi_params* p, rexi_plan** out) {
         hipError_t e = hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming);
         if (e != hipSuccess) rc = hip_fail(e, "hipEventCreateWithFlags");
     }
+    if (!rc) {
+        hipError_t e = hipGetDevice(&pl->device);
+        if (e != hipSuccess) rc = hip_fail(e, "hipGetDevice");
+    }
+    // the no-allocation step's workspace on this device (looked up once per device)
+    if (!rc) rc = scratch_setup(&pl->scratch, &pl->scratch_bytes);
     if (!rc && p->nlat > 0) rc = sh_setup(pl);
     if (rc) {
         release(pl);
@@ -770,10 +763,11 @@ int rexi_step_per_term(rexi_plan* plan, const void* u0, void* u1, int S, void* s
             plan->acc_capacity = sc.part_size;
         }
         hipStream_t s = (hipStream_t)stream;
-        REXI_HIP(enqueue_prep(plan, u0, 0, S, 0, plan->sched_layout, s));
+        const Workspace ws = plan_workspace(plan);
+        REXI_HIP(enqueue_prep(plan, ws, u0, 0, S, 0, plan->sched_layout, s));
         REXI_HIP(enqueue_zero(plan->d_acc, sc.part_size, s));
-        for (int k = 0; k < plan->N; ++k) REXI_HIP(enqueue_per_term_pole(plan, sc, k, 0, S, s));
-        REXI_HIP(enqueue_reduce(plan, sc, plan->d_acc, 0, 1, u1, S, 0, plan->d_slot_m, s));
+        for (int k = 0; k < plan->N; ++k) REXI_HIP(enqueue_per_term_pole(plan, ws, sc, k, 0, S, s));
+        REXI_HIP(enqueue_reduce(plan, ws, sc, plan->d_acc, 0, 1, u1, S, 0, plan->d_slot_m, s));
         return REXI_OK;
     } catch (const std::bad_alloc&) {
         return fail(REXI_ENOMEM, "host allocation failed");

@@ -1128,17 +1128,18 @@ int solve_variant_list(bool per_term, int* se, int* kind, int* st, int cap) {
 }
 
 // Internal launchers used by the C ABI (plan.cpp).
-hipError_t enqueue_prep(rexi_plan* pl, const void* u, int buf, int S, int adjoint, const MInfo* d_layout,
-                        hipStream_t s) {
+hipError_t enqueue_prep(rexi_plan* pl, const Workspace& ws, const void* u, int buf, int S, int adjoint,
+                        const MInfo* d_layout, hipStream_t s) {
     const long long n = (long long)S * pl->nspec;
     const int bs = 256;
     hipLaunchKernelGGL(k_prep, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, (const double2*)u,
-                       pl->d_ch_var[buf], pl->d_ch_phi[buf], d_layout, pl->d_idx_n, pl->d_idx_m, pl->d_sc,
+                       ws.ch_var[buf], ws.ch_phi[buf], d_layout, pl->d_idx_n, pl->d_idx_m, pl->d_sc,
                        adjoint, S, pl->nspec, pl->nslots + 2, pl->nslots);
     return hipGetLastError();
 }
 
-hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int adjoint, hipStream_t s) {
+hipError_t enqueue_solve(rexi_plan* pl, const Workspace& ws, const Schedule& sc, int buf, int S, int adjoint,
+                         hipStream_t s) {
     SolveArgs a;
     a.items = sc.d_items;
     a.minfo = sc.d_minfo;
@@ -1146,9 +1147,9 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
     a.om = pl->d_om;
     a.cc = pl->d_cc;
     a.poles = reinterpret_cast<const PoleData*>(pl->d_poles[adjoint]);
-    a.ch_var = pl->d_ch_var[buf];
-    a.ch_phi = pl->d_ch_phi[buf];
-    a.part = pl->d_part;
+    a.ch_var = ws.ch_var[buf];
+    a.ch_phi = ws.ch_phi[buf];
+    a.part = ws.part;
     a.T = pl->T;
     a.S = S;
     a.var_stride = pl->nslots + 2;
@@ -1156,14 +1157,14 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
     if (sc.persistent) {
         const int n = (int)sc.launches.size();
         if (n > kMaxLaunches) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, pl->d_counters, n);
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, ws.counters, n);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     const int nl = (int)sc.launches.size();
     if (!pl->concurrent || nl < 2) {
         for (int c = 0; c < nl; ++c) {
-            hipError_t e = launch_solve<false>(sc.launches[c], a, sc.persistent ? pl->d_counters + c : nullptr, s);
+            hipError_t e = launch_solve<false>(sc.launches[c], a, sc.persistent ? ws.counters + c : nullptr, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1174,15 +1175,15 @@ hipError_t enqueue_solve(rexi_plan* pl, const Schedule& sc, int buf, int S, int 
     for (int c = 0; c < nl && e == hipSuccess; ++c) {
         e = hipStreamWaitEvent(pl->side[c], pl->fork_ev, 0);
         if (e == hipSuccess)
-            e = launch_solve<false>(sc.launches[c], a, sc.persistent ? pl->d_counters + c : nullptr, pl->side[c]);
+            e = launch_solve<false>(sc.launches[c], a, sc.persistent ? ws.counters + c : nullptr, pl->side[c]);
         if (e == hipSuccess) e = hipEventRecord(pl->join_ev[c], pl->side[c]);
     }
     for (int c = 0; c < nl && e == hipSuccess; ++c) e = hipStreamWaitEvent(s, pl->join_ev[c], 0);
     return e;
 }
 
-hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part, int buf_in, int buf_out,
-                          void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s) {
+hipError_t enqueue_reduce(rexi_plan* pl, const Workspace& ws, const Schedule& sc, const double2* part, int buf_in,
+                          int buf_out, void* u_out, int S, int adjoint, const int* d_slot_m, hipStream_t s) {
     ReduceArgs r;
     r.minfo = sc.d_minfo;
     r.groups = sc.d_groups;
@@ -1190,10 +1191,10 @@ hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part
     r.om = pl->d_om;
     r.sc = pl->d_sc;
     r.part = part;
-    r.ch_var_in = pl->d_ch_var[buf_in];
-    r.ch_phi_in = pl->d_ch_phi[buf_in];
-    r.ch_var_out = u_out ? nullptr : pl->d_ch_var[buf_out];
-    r.ch_phi_out = u_out ? nullptr : pl->d_ch_phi[buf_out];
+    r.ch_var_in = ws.ch_var[buf_in];
+    r.ch_phi_in = ws.ch_phi[buf_in];
+    r.ch_var_out = u_out ? nullptr : ws.ch_var[buf_out];
+    r.ch_phi_out = u_out ? nullptr : ws.ch_phi[buf_out];
     r.u_out = (double2*)u_out;
     r.S = S;
     r.invert_scale = adjoint;
@@ -1210,12 +1211,12 @@ hipError_t enqueue_reduce(rexi_plan* pl, const Schedule& sc, const double2* part
     return hipGetLastError();
 }
 
-hipError_t enqueue_finish(rexi_plan* pl, int buf, void* u, int S, int adjoint, const MInfo* d_layout,
-                          hipStream_t s) {
+hipError_t enqueue_finish(rexi_plan* pl, const Workspace& ws, int buf, void* u, int S, int adjoint,
+                          const MInfo* d_layout, hipStream_t s) {
     const long long n = (long long)S * pl->nspec;
     const int bs = 256;
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, pl->d_ch_var[buf],
-                       pl->d_ch_phi[buf], (double2*)u, d_layout, pl->d_idx_n, pl->d_idx_m, pl->d_sc, adjoint, S,
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, ws.ch_var[buf],
+                       ws.ch_phi[buf], (double2*)u, d_layout, pl->d_idx_n, pl->d_idx_m, pl->d_sc, adjoint, S,
                        pl->nspec, pl->nslots + 2, pl->nslots);
     return hipGetLastError();
 }
@@ -1237,7 +1238,8 @@ hipError_t enqueue_zero(double2* p, long long n, hipStream_t s) {
 
 // Per-term form: one launch per pole over all (m, p, tile) items, each adding
 // its pole's weighted solution into the accumulator (fixed pole order).
-hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int buf, int S, hipStream_t s) {
+hipError_t enqueue_per_term_pole(rexi_plan* pl, const Workspace& ws, const Schedule& sc, int k, int buf, int S,
+                                 hipStream_t s) {
     SolveArgs a;
     a.items = sc.d_items;
     a.minfo = sc.d_minfo;
@@ -1245,8 +1247,8 @@ hipError_t enqueue_per_term_pole(rexi_plan* pl, const Schedule& sc, int k, int b
     a.om = pl->d_om;
     a.cc = pl->d_cc;
     a.poles = reinterpret_cast<const PoleData*>(pl->d_poles[0]) + k;
-    a.ch_var = pl->d_ch_var[buf];
-    a.ch_phi = pl->d_ch_phi[buf];
+    a.ch_var = ws.ch_var[buf];
+    a.ch_phi = ws.ch_phi[buf];
     a.part = pl->d_acc;
     a.T = pl->T;
     a.S = S;

@@ -53,6 +53,7 @@ def load_library():
         "rexi_step": [P, P, P, c_int, c_int, P],
         "rexi_step_adjoint": [P, P, P, c_int, c_int, P],
         "rexi_step_per_term": [P, P, P, c_int, P],
+        "rexi_step_noalloc": [P, P, P, c_int, c_int, P],
         "rexi_plan_autotune": [P, c_int, P, POINTER(c_int)],
         "rexi_plan_set_schedule": [P, c_int, c_int, POINTER(c_int)],
         "rexi_plan_set_timing": [P, c_int],
@@ -189,6 +190,11 @@ class Plan:
     def step_adjoint(self, g1, nsteps: int = 1, out=None, stream=None):
         """g0 = (R^H)^nsteps g1 (rexi_step_adjoint)."""
         return self._state_call(self._lib.rexi_step_adjoint, "rexi_step_adjoint", g1, nsteps, out, stream)
+
+    def step_noalloc(self, u0, nsteps: int = 1, out=None, stream=None):
+        """u1 = R^nsteps u0 with the library's fixed workspace (rexi_step_noalloc).
+        ``out`` must be given by callers that cannot allocate."""
+        return self._state_call(self._lib.rexi_step_noalloc, "rexi_step_noalloc", u0, nsteps, out, stream)
 
     def step_per_term(self, u0, out=None, stream=None):
         """One step in the plain per-term launch form (rexi_step_per_term)."""
