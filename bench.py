@@ -449,6 +449,9 @@ def main():
                      "algorithmic_bytes_per_launch": state_bytes,
                      "algorithmic_GBps": state_bytes / avg_solve_s / 1e9,
                      "traffic_GBps": (traffic / avg_solve_s / 1e9) if traffic else None,
+                     "traffic_k_solve_classes": tr.get("k_solve_classes_bytes_per_launch") if tr else None,
+                     "traffic_earlier_MB": ([(r["kernel_source_sha256_16"], r["schedule"], r["MB_per_step"], r["what"])
+                                             for r in tr.get("earlier_readings", {}).get("runs", [])] if tr else None),
                      "executed_fp64_flops_per_launch": ctr.get("executed_fp64_flops_per_step") if ctr else None,
                      "kernel_source_sha256_16": digest},
         "per_term_hbm": per_term_hbm,

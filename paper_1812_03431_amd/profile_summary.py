@@ -75,7 +75,28 @@ def calibration(path, counter):
     return max(vals)
 
 
-def traffic(fetch_csv, write_csv, schedule, workload, commands):
+def earlier_readings(path):
+    """The readings of an existing traffic summary (its own and the ones it
+    carried), so that a new run keeps the history: a list of
+    {source hash, schedule, MB per step, what}."""
+    try:
+        with open(path) as f:
+            old = json.load(f)
+    except (OSError, ValueError):
+        return []
+    runs = list(old.get("earlier_readings", {}).get("runs", []))
+    if "traffic_bytes_per_launch" in old:
+        runs.append({"kernel_source_sha256_16": old.get("kernel_source_sha256_16"), "schedule": old.get("schedule"),
+                     "MB_per_step": round(old["traffic_bytes_per_launch"] / 1e6, 2),
+                     "what": "k_solve class launches and k_reduce of one step"})
+        if "k_solve_classes_bytes_per_launch" in old:
+            runs.append({"kernel_source_sha256_16": old.get("kernel_source_sha256_16"), "schedule": old.get("schedule"),
+                         "MB_per_step": round(old["k_solve_classes_bytes_per_launch"] / 1e6, 2),
+                         "what": "k_solve class launches only (no reduction)"})
+    return runs
+
+
+def traffic(fetch_csv, write_csv, schedule, workload, commands, earlier=()):
     GiB_KiB = float(1 << 20)
     fcal, wcal = calibration(fetch_csv, "FETCH_SIZE"), calibration(write_csv, "WRITE_SIZE")
     fscale, wscale = GiB_KiB / fcal, GiB_KiB / wcal
@@ -89,12 +110,14 @@ def traffic(fetch_csv, write_csv, schedule, workload, commands):
                     cls[c][key].append(v)
         out[kind] = cls
     per_class = {}
-    step = 0.0
+    step = solve_only = 0.0
     for c, v in out["batched"].items():
         f = sum(v["fetch_kib"]) / max(1, len(v["fetch_kib"]))
         w = sum(v["write_kib"]) / max(1, len(v["write_kib"]))
         per_class[c] = {"fetch_kib_mean": f, "write_kib_mean": w, "dispatches": len(v["fetch_kib"])}
         step += (f * fscale + w * wscale) * 1024.0
+        if c != "k_reduce":
+            solve_only += (f * fscale + w * wscale) * 1024.0
     pt_f = sum(sum(v["fetch_kib"]) for v in out["per_term"].values())
     pt_w = sum(sum(v["write_kib"]) for v in out["per_term"].values())
     pt_n = sum(len(v["fetch_kib"]) for v in out["per_term"].values())
@@ -106,8 +129,13 @@ def traffic(fetch_csv, write_csv, schedule, workload, commands):
              "workload": workload, "schedule": schedule, "kernel_source_sha256_16": digest,
              "commands": commands, "calibration": cal, "per_class": per_class,
              "traffic_bytes_per_launch": step,
+             "k_solve_classes_bytes_per_launch": solve_only,
              "note": "one launch = one step; bytes = sum over the step's kernels of the mean per dispatch of "
-                     "FETCH_SIZE*fetch_scale + WRITE_SIZE*write_scale (KiB -> bytes)"}
+                     "FETCH_SIZE*fetch_scale + WRITE_SIZE*write_scale (KiB -> bytes)",
+             "earlier_readings": {"note": "the same two counter runs on earlier versions of the solve kernel "
+                                          "(source hash, schedule); the spread of repeated runs on one kernel "
+                                          "shows in the entries that share a hash",
+                                  "runs": list(earlier)}}
     per_term = {"kernel": "k_solve per-term launches (one per pole and class) of one per-term step",
                 "workload": workload, "kernel_source_sha256_16": digest, "commands": commands,
                 "calibration": cal, "dispatches": pt_n, "fetch_kib_total": pt_f, "write_kib_total": pt_w,
@@ -202,7 +230,7 @@ def main():
         with open(a.out, "w") as f:
             f.write(stats(a.stats, a.trace, a.schedule, a.workload, " ".join(a.command), a.events_ms))
     elif a.what == "traffic":
-        solve, per_term = traffic(a.fetch, a.write, a.schedule, a.workload, a.command)
+        solve, per_term = traffic(a.fetch, a.write, a.schedule, a.workload, a.command, earlier_readings(a.out_solve))
         with open(a.out_solve, "w") as f:
             json.dump(solve, f, indent=1)
         with open(a.out_per_term, "w") as f:
