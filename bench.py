@@ -332,7 +332,9 @@ def main():
     elif not args.no_autotune:
         chosen = plan.autotune(S)
     else:
-        chosen = None
+        chosen = plan.chosen_schedule(S)
+    sched_name = plan.schedule_name(S, chosen)
+    sched_classes = plan.schedule_classes(S, chosen)
     torch.cuda.synchronize()
 
     def job():
@@ -347,7 +349,7 @@ def main():
             g = plan.step_adjoint(g, ck)
         return plan.sh_inverse(g.view(B, plan.nspec))
 
-    stage(f"schedule {chosen}; warm-up")
+    stage(f"schedule {chosen} ({sched_name}); warm-up")
     for _ in range(args.warmup):
         job()
     torch.cuda.synchronize()
@@ -433,6 +435,8 @@ def main():
                    "h": w.h, "poles": N, "states": S, "forward_steps": w.steps, "adjoint_steps": w.steps,
                    "checkpoint_every": ck, "sh_fields": B, "blocks_per_step": blocks_per_job},
         "schedule": chosen,
+        "schedule_name": sched_name,
+        "schedule_classes": [list(c) for c in sched_classes],
         "timed_path": "step graphs on; HIP events around each step graph and Legendre launch",
         "rexi_step_ms": avg_solve_s * 1e3,
         "fwd_plus_adjoint_step_ms": 2 * avg_solve_s * 1e3,

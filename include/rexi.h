@@ -250,6 +250,14 @@ int rexi_solve_variants(int per_term, int capacity, int *se, int *kind, int *sta
 int rexi_plan_schedule_classes(rexi_plan *plan, int S, int index, int capacity, int *se, int *kind,
                                int *states_per_item, int *count);
 
+/* The name of schedule candidate `index` for S states (-1 = the per-term
+ * schedule, once built): tile policy, work-item count, "persistent_" for a
+ * grid of resident workgroups pulling items from a counter, and "_shared" /
+ * "_mixed" where states share each pole's factorisation in every / some of
+ * its tile classes (no suffix: in none).  Written NUL-terminated into buf (host, capacity bytes, truncated
+ * to fit); REXI_EINVAL for a NULL buf or capacity < 1. */
+int rexi_plan_schedule_name(rexi_plan *plan, int S, int index, char *buf, int capacity);
+
 /* Step graphs.  By default every step is replayed as a captured HIP graph
  * (solve launches + reduction), built on first use per (S, direction, buffer)
  * and rebuilt after a schedule change; enable = 0 makes the plan launch the

@@ -268,9 +268,13 @@ int build_schedule(rexi_plan* pl, int S, int policy, long long target_items, boo
         out.launches.push_back(L);
     }
     out.part_size = off;
+    // "_shared": every class shares factorisations among states, "_mixed": some do
+    int nshare = 0;
+    for (const Cls& c : classes) nshare += c.rot > 1;
+    const char* share_tag = nshare == 0 ? "" : nshare == (int)classes.size() ? "_shared" : "_mixed";
     char buf[96];
-    std::snprintf(buf, sizeof buf, "%s_items%lld%s%s", kPolicyName[policy], (long long)out.items.size(),
-                  rot_mode == 1 ? "_shared" : rot_mode == 2 ? "_mixed" : "", per_term ? "_perterm" : "");
+    std::snprintf(buf, sizeof buf, "%s_items%lld%s%s", kPolicyName[policy], (long long)out.items.size(), share_tag,
+                  per_term ? "_perterm" : "");
     out.name = buf;
     int rc = upload(&out.d_minfo, out.minfo);
     if (!rc) rc = upload(&out.d_items, out.items);
@@ -881,6 +885,28 @@ int rexi_plan_schedule_classes(rexi_plan* plan, int S, int index, int capacity, 
         if (states_per_item) states_per_item[i] = sc->launches[i].rot;
     }
     if (count) *count = n;
+    return REXI_OK;
+}
+
+int rexi_plan_schedule_name(rexi_plan* plan, int S, int index, char* buf, int capacity) {
+    if (!plan) return fail(REXI_EINVAL, "plan is NULL");
+    if (!buf || capacity < 1) return fail(REXI_EINVAL, "buf is NULL or capacity < 1");
+    buf[0] = 0;
+    if (plan->prm.fsphere) return fail(REXI_EUNSUPPORTED, "f-sphere plans have no schedules");
+    if (S < 1 || S > plan->prm.max_states) return fail(REXI_EINVAL, "S out of range");
+    const Schedule* sc = nullptr;
+    if (index == -1) {
+        if ((int)plan->per_term.size() <= S || plan->per_term[S].items.empty())
+            return fail(REXI_EINVAL, "the per-term schedule for S is built by the first rexi_step_per_term call");
+        sc = &plan->per_term[S];
+    } else {
+        std::vector<Schedule>* c = nullptr;
+        int rc = schedules_for(plan, S, &c);
+        if (rc) return rc;
+        if (index < -1 || index >= (int)c->size()) return fail(REXI_EINVAL, "schedule index out of range");
+        sc = &(*c)[index];
+    }
+    std::snprintf(buf, (size_t)capacity, "%s", sc->name.c_str());
     return REXI_OK;
 }
 

@@ -265,8 +265,7 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
 // recurrence P_n = a_n mu P_{n-1} - b_n P_{n-2}, restarted every kRun degrees
 // from exact host values, which keeps the FP64 recurrence error at a few ulp.
 constexpr int kRun = 32;         // degrees per restart row of the table
-constexpr int kInvRun = 64;      // degrees between the inverse's restarts (a multiple of kRun)
-constexpr int kInvSeg = 128;     // degrees per inverse work item (a multiple of kInvRun)
+constexpr int kInvSeg = 4 * kRun;  // degrees per inverse work item: four runs, the MFMA's k index
 constexpr int kFwdDeg = 32;      // degrees per forward run: two 16-row parity tiles
 constexpr int kFwdLat = 128;     // latitudes per generated forward block
 constexpr int kPtPitch = kFwdLat + 1;  // LDS row pitch of the generated tile (odd: spreads banks)
@@ -292,18 +291,31 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// FP64 MFMA of four independent 4x4x4 blocks (v_mfma_f64_4x4x4f64): with
+// lane = 16 q + 4 b + p, block b takes A[i = p][k = q], B[k = q][j = p] and
+// returns D[i = q][j = p] (layout checked on the GPU).  On this part it keeps
+// the matrix pipe near its FP64 rate with one or two waves per SIMD, where the
+// 16x16x4 shape needs about eight; and four-column groups fit any even column
+// count with at most two idle columns.
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
 // Forward: out[b][idx(m, n)] = sum_{j<H} P_n^m(mu_j) EO[m][r][j][c], r the
 // parity of n - m (EO holds the Gauss-weighted even / odd Fourier parts),
-// over the runs of one work item.  Wave w = 2 h + r owns output tile (degree
-// parity r, column tile h) and keeps its B fragments, EO[m][r][j][c] for its
-// lane's column and latitudes j = 4 s + lane/16, in registers for the whole
-// work item (one latitude block; larger grids reload them per block).  Per
-// run the first kFwdLat threads generate the 32 degrees of their latitude
-// into Pt[d][lat] (pitch kPtPitch), one barrier, then every wave runs its 32
-// MFMA k-steps with A from Pt; the next run's restart values and recurrence
-// coefficients (lane d holds degree n0 + d + 1, broadcast by readlane) are
-// loaded before the MFMAs.  Columns [c_off, c_off + C) of EO (row stride Cs),
-// C <= 32.
+// over the runs of one work item.  Per run the first kFwdLat threads generate
+// the 32 degrees of their latitude into Pt[d][lat] (pitch kPtPitch), one
+// barrier, then every wave contracts.  Wave w = 2 h + r owns degree parity r
+// (16 degrees per run, four groups of 4) and the column groups [h NH,
+// h NH + NH) of 4 columns.  Its MFMA blocks split the latitude sum: block b
+// of k-step s takes latitudes 16 s + 4 b + q, so a lane's B operands are
+// EO[16 s + 4 b + q][4 g + p], 8 x NH values per 128 latitudes, held in
+// registers for the whole work item (larger grids reload them per block); the
+// four blocks' partial sums are added across the row at the end of a run.
+// The next run's restart values and recurrence coefficients (lane d holds
+// degree n0 + d + 1, broadcast by readlane) are loaded before the MFMAs.
+// Columns [c_off, c_off + C) of EO (row stride Cs), C <= 32.
+template <int NH>
 __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restrict__ runs,
                                                           const double* __restrict__ restart,
                                                           const double2* __restrict__ coef,
@@ -316,13 +328,15 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
     const int m = rn.m;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int i = lane & 15, kq = lane >> 4;
-    const int r = wave & 1, h = wave >> 1;  // degree parity and column tile of this wave
-    const int col = h * 16 + i;
-    const bool cok = col < C;
+    const int p = lane & 3, bq = (lane >> 2) & 3, q = lane >> 4;
+    const int r = wave & 1, h = wave >> 1;  // degree parity and column half of this wave
+    const bool busy = h * NH * 4 < C;        // the wave has columns
     const long long so = spec_offset(T, m);
     const long long ns = nspec_of(T);
-    const double* Bsrc = EO + (long long)(m * 2 + r) * eo_plane(H, Cs) + c_off + min(col, C - 1);
+    const double* Bsrc = EO + (long long)(m * 2 + r) * eo_plane(H, Cs) + c_off;
+    int bcol[NH];
+#pragma unroll
+    for (int g = 0; g < NH; ++g) bcol[g] = min(4 * (h * NH + g) + p, C - 1);
     const int nblk = (H + kFwdLat - 1) / kFwdLat;
     const int nit = rn.nrun * nblk;  // (run, latitude block) iterations
     const bool gen = tid < kFwdLat;
@@ -341,16 +355,23 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
     double pm_n, pc_n, x_n;
     double2 ab_n;
     fetch(0, pm_n, pc_n, x_n, ab_n);
-    double bf[kFwdLat / 4];
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    double bf[kFwdLat / 16][NH];
+    double acc[4][NH];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int g = 0; g < NH; ++g) acc[d][g] = 0.0;
+    // A operand of degree group d, k-step s: Pt row 2 (4 d + p) + r, latitude 16 s + 4 bq + q
+    const double* Ap = Pt + (2 * p + r) * kPtPitch + 4 * bq + q;
     for (int it = 0; it < nit; ++it) {
         const int g = it / nblk, blk = it - g * nblk;
         const int lb = blk * kFwdLat;
         if (it == 0 || nblk > 1) {
 #pragma unroll
-            for (int q = 0; q < kFwdLat / 4; ++q) {
-                const int j = lb + 4 * q + kq;
-                bf[q] = (j < H) ? Bsrc[(long long)j * Cs] : 0.0;
+            for (int s = 0; s < kFwdLat / 16; ++s) {
+                const int j = lb + 16 * s + 4 * bq + q;
+#pragma unroll
+                for (int c = 0; c < NH; ++c) bf[s][c] = (j < H) ? Bsrc[(long long)j * Cs + bcol[c]] : 0.0;
             }
         }
         if (it > 0) __syncthreads();  // the previous tile is consumed
@@ -369,32 +390,37 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
         }
         if (it + 1 < nit) fetch(it + 1, pm_n, pc_n, x_n, ab_n);
         __syncthreads();
-        const double* Ap = Pt + (2 * i + r) * kPtPitch + kq;
+        if (busy) {
 #pragma unroll
-        for (int q0 = 0; q0 < kFwdLat / 4; q0 += 8) {
-            double av[8];
+            for (int s = 0; s < kFwdLat / 16; ++s) {
+                double av[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) av[u] = Ap[4 * (q0 + u)];
-            __builtin_amdgcn_sched_barrier(0);  // the chunk's reads ahead of its MFMAs
+                for (int d = 0; d < 4; ++d) av[d] = Ap[8 * d * kPtPitch + 16 * s];
 #pragma unroll
-            for (int u = 0; u < 8; u += 2) {
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bf[q0 + u], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bf[q0 + u + 1], acc1, 0, 0, 0);
+                for (int d = 0; d < 4; ++d)
+#pragma unroll
+                    for (int c = 0; c < NH; ++c) acc[d][c] = mfma4(av[d], bf[s][c], acc[d][c]);
             }
         }
         if (blk == nblk - 1) {
-            // accumulator register rr of lane l holds D[4 rr + l/16][l % 16]
+            // lane 16 q + 4 bq + p holds block bq's partial D[degree q][column p]
+            // of each group; the row's four blocks are added by two exchanges
             const int n0 = rn.n0 + kFwdDeg * g;
-            if (cok) {
-                const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const int n = n0 + 2 * (4 * rr + kq) + r;
-                    if (n <= T) spec[((long long)b * ns + so + (n - m)) * 2 + ri] = acc0[rr] + acc1[rr];
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int c = 0; c < NH; ++c) {
+                    double v = acc[d][c];
+                    v += __shfl_xor(v, 4);
+                    v += __shfl_xor(v, 8);
+                    acc[d][c] = 0.0;
+                    const int col = 4 * (h * NH + c) + p;
+                    const int n = n0 + 2 * (4 * d + q) + r;
+                    if (busy && bq == 0 && col < C && n <= T) {
+                        const int b = (c_off + col) >> 1, ri = (c_off + col) & 1;
+                        spec[((long long)b * ns + so + (n - m)) * 2 + ri] = v;
+                    }
                 }
-            }
-            acc0 = v4d{0.0, 0.0, 0.0, 0.0};
-            acc1 = v4d{0.0, 0.0, 0.0, 0.0};
         }
     }
 }
@@ -402,22 +428,27 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
 // Inverse: over one degree segment of order m, Fw[slot][j] = Fe + Fo,
 // Fw[slot][j'] = Fe - Fo with Fe / Fo the sums of P_n^m(mu_j) S_n over the
 // segment's n with n - m even / odd (the inverse FFT adds the segments of an
-// order).  Segments of at most kInvSeg degrees bound the serial work of a wave
-// and the block a workgroup stages.  A workgroup takes up to four 16-latitude
-// tiles (one wave each) and stages in LDS the segment's spectral block
-// Sm [Ls][C], its coefficient column and the exact restart values of its 64
-// latitudes at every kInvRun-th degree.  Lanes (i = lane & 15, kq = lane >> 4)
-// run the recurrence of latitude i in registers (the four kq lanes alike) and
-// keep what their MFMA fragment needs: per k-step of 8 degrees
-// base .. base + 7, A_even = P_{base + 2 kq}, A_odd = P_{base + 2 kq + 1}.
+// order).  A segment is four kRun-degree runs; a workgroup takes up to four
+// 16-latitude tiles (one wave each) and stages in LDS the segment's spectral
+// block Sm [Ls][C], its coefficient column and the exact restart values of
+// its 64 latitudes at the start of each run.  The runs are the k index of the
+// four-block MFMA: lane 16 kq + i (i < 16) runs the recurrence of latitude i
+// over run kq from its own restart values, so no two lanes repeat a
+// recurrence and no lane selects values, and per k-step s it holds
+// A_even = P at run degree 2 s and A_odd = P at 2 s + 1 (run starts are a
+// multiple of kRun from m, so the parity of n - m is that of the run degree).
+// In the MFMA that lane is A[i & 3][kq] of block i >> 2: latitude i of the
+// tile.  The blocks share B, the segment's coefficients
+// S[32 kq + 2 s (+1)][4 g + (lane & 3)] of column group g, and the result
+// D[q][p] of lane 16 q + 4 b + p is latitude 4 b + q, column 4 g + p.
 // Degrees past the segment need no checks: their coefficients are zero, so P
-// is zero there, and the B reads are clamped into the block.  (Summing a
-// half-empty second column tile on the VALU instead of the MFMA pipe measured
-// slower: 22.3 vs 21.0 us at T256, 24 columns.)
+// is zero there, and the B reads are clamped into the block; runs that start
+// past the order's last degree have zero restart values.
 
 // Stage the spectral block of degrees m + n0 .. m + n0 + Ls - 1 ([Ls][C],
-// columns c_off..) and its coefficient column ([Ls + 16], cf[k] for degree
-// m + n0 + k, zero outside 1 <= k < Ls).  The coefficients of one field form
+// columns c_off..) and its coefficient column ([kInvSeg + 16], cf[k] for
+// degree m + n0 + k, zero outside 1 <= k < Ls, so that every run's recurrence
+// reads staged values up to its end).  The coefficients of one field form
 // a contiguous run of 2 Ls <= 256 doubles: thread k takes double k of every
 // field (coalesced), all loads before the stores.
 __device__ __forceinline__ void stage_segment(long long so, long long ns, int Ls, int C, int c_off,
@@ -433,11 +464,11 @@ __device__ __forceinline__ void stage_segment(long long so, long long ns, int Ls
 #pragma unroll
     for (int f = 0; f < 16; ++f)
         if (ok && f < nb) Sm[(k >> 1) * C + 2 * f + (k & 1)] = v[f];  // degree k/2, column 2f + re/im
-    for (int q = threadIdx.x; q < Ls + 16; q += blockDim.x)
+    for (int q = threadIdx.x; q < kInvSeg + 16; q += blockDim.x)
         cf[q] = (q >= 1 && q < Ls) ? coef[so + q] : make_double2(0.0, 0.0);
 }
 
-template <int NCT>
+template <int NG>
 __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restrict__ work,
                                                           const double* __restrict__ restart,
                                                           const double2* __restrict__ coef,
@@ -450,72 +481,59 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     if (wk.m < 0) return;  // padding slot of the XCD-ordered list
     const int m = wk.m;
     const int Ls = min(kInvSeg, T + 1 - m - wk.n0);  // degrees of this segment
-    const int nr = (Ls + kInvRun - 1) / kInvRun;       // restarts of this segment
+    const int nr = (Ls + kRun - 1) / kRun;             // runs of this segment that hold degrees
     double* Sm = lds;                                        // [Ls][C]
-    double2* cf = reinterpret_cast<double2*>(lds + Ls * C);  // [Ls + 16] (Ls * C is even: C is)
-    double* Rs = lds + Ls * C + 2 * (Ls + 16);               // [nr][2][64]
+    double2* cf = reinterpret_cast<double2*>(lds + Ls * C);  // [kInvSeg + 16] (Ls * C is even: C is)
+    double* Rs = lds + Ls * C + 2 * (kInvSeg + 16);          // [4][2][64]
     stage_segment(spec_offset(T, m) + wk.n0, nspec_of(T), Ls, C, c_off, spec, coef, Sm, cf);
     const int jw = wk.t0 * 16;  // first latitude of the workgroup
-    for (int k = threadIdx.x; k < nr * 128; k += blockDim.x) {
+    for (int k = threadIdx.x; k < 4 * 128; k += blockDim.x) {
         const int r = k >> 7, w = (k >> 6) & 1, j = min(jw + (k & 63), H - 1);
-        Rs[k] = restart[((long long)(wk.run0 + r * (kInvRun / kRun)) * 2 + w) * H + j];
+        Rs[k] = (r < nr) ? restart[((long long)(wk.run0 + r) * 2 + w) * H + j] : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t = wk.t0 + wave;
     if (t >= wk.t1) return;  // no latitude tile for this wave (no barrier follows)
-    const int i = lane & 15, kq = lane >> 4;
+    const int i = lane & 15, kq = lane >> 4, p = lane & 3;
     const int j = t * 16 + i;
     const double x = (j < H) ? mu[j] : 0.0;
-    const int c0 = min(i, C - 1), c1 = min(16 + i, C - 1);
-    v4d ae0 = {0.0, 0.0, 0.0, 0.0}, ao0 = ae0, ae1 = ae0, ao1 = ae0;
-    for (int r = 0; r < nr; ++r) {
-        double pv = Rs[(r * 2) * 64 + wave * 16 + i];
-        double cu = Rs[(r * 2 + 1) * 64 + wave * 16 + i];
-        const int kr = r * kInvRun;
+    const int rb = kq * kRun;  // first segment degree of this lane's run
+    double pv = Rs[(kq * 2) * 64 + wave * 16 + i];
+    double cu = Rs[(kq * 2 + 1) * 64 + wave * 16 + i];
+    double ae[NG], ao[NG];
 #pragma unroll
-        for (int ks = 0; ks < kInvRun; ks += 8) {
-            const int kb = kr + ks;
-            if (kb >= Ls) break;
-            double2 cv[8];
+    for (int g = 0; g < NG; ++g) ae[g] = ao[g] = 0.0;
+#pragma unroll 4
+    for (int s = 0; s < kRun / 2; ++s) {
+        const int d = rb + 2 * s;                          // even run degree (segment-relative)
+        const double2 c1 = cf[d + 1], c2 = cf[d + 2];      // d + 2 <= kInvSeg
+        const double* be = Sm + min(d, Ls - 1) * C + p;
+        const double* bo = Sm + min(d + 1, Ls - 1) * C + p;
+        const double a_e = cu;
+        const double a_o = fma(c1.x * x, cu, -c1.y * pv);
+        cu = fma(c2.x * x, a_o, -c2.y * a_e);
+        pv = a_o;
 #pragma unroll
-            for (int d = 0; d < 8; ++d) cv[d] = cf[kb + d + 1];  // < Ls + 16
-            const int de = min(kb + 2 * kq, Ls - 1), dd = min(kb + 2 * kq + 1, Ls - 1);
-            const double b0 = Sm[de * C + c0], b1 = Sm[dd * C + c0];
-            const double b2 = Sm[de * C + c1], b3 = Sm[dd * C + c1];
-            double a_e = 0.0, a_o = 0.0;
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? cu : a_e;
-                else a_o = (kq == (d >> 1)) ? cu : a_o;
-                const double nx = fma(cv[d].x * x, cu, -cv[d].y * pv);
-                pv = cu;
-                cu = nx;
-            }
-            ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, b0, ae0, 0, 0, 0);
-            ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, b1, ao0, 0, 0, 0);
-            if constexpr (NCT > 1) {
-                ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, b2, ae1, 0, 0, 0);
-                ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, b3, ao1, 0, 0, 0);
-            }
+        for (int g = 0; g < NG; ++g) {
+            const int cg = min(4 * g, C - 1 - p);  // column 4 g + p, clamped into the block
+            ae[g] = mfma4(a_e, be[cg], ae[g]);
+            ao[g] = mfma4(a_o, bo[cg], ao[g]);
         }
     }
-    // accumulator register q of lane l holds D[4 q + l/16][l % 16]: latitude
-    // row 4 q + kq of the tile, column l % 16 of the column tile
+    // lane 16 q + 4 b + p holds latitude 4 b + q of the tile, column 4 g + p
+    const int jj = t * 16 + 4 * ((lane >> 2) & 3) + kq;
+    if (jj < H) {
+        double* fn = Fw + wk.slot * slot_plane(nlat, Cs) + (long long)jj * Cs + c_off;
+        double* fs = Fw + wk.slot * slot_plane(nlat, Cs) + (long long)(nlat - 1 - jj) * Cs + c_off;
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-        const int col = hh * 16 + i;
-        if (hh >= NCT || col >= C) continue;
-        const v4d ae = hh ? ae1 : ae0, ao = hh ? ao1 : ao0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int jj = t * 16 + 4 * q + kq;
-            if (jj < H) {
+        for (int g = 0; g < NG; ++g) {
+            const int col = 4 * g + p;
+            if (col < C) {
                 // streaming stores: the partials go out while the kernel runs
                 // instead of as dirty L2 lines written back at its end
-                __builtin_nontemporal_store(ae[q] + ao[q], Fw + wk.slot * slot_plane(nlat, Cs) + (long long)jj * Cs + c_off + col);
-                __builtin_nontemporal_store(ae[q] - ao[q],
-                                            Fw + wk.slot * slot_plane(nlat, Cs) + (long long)(nlat - 1 - jj) * Cs + c_off + col);
+                __builtin_nontemporal_store(ae[g] + ao[g], fn + col);
+                __builtin_nontemporal_store(ae[g] - ao[g], fs + col);
             }
         }
     }
@@ -598,9 +616,9 @@ __global__ void __launch_bounds__(256) k_uv_spec_to_vd(const double2* __restrict
 
 
 // Inverse LDS: a segment's block [kInvSeg][w], coefficient column and restart
-// values (2 x 64 latitudes per kInvRun degrees).
+// values (2 x 64 latitudes per run).
 size_t inverse_lds(int w) {
-    return sizeof(double) * ((size_t)kInvSeg * w + 2 * (size_t)(kInvSeg + 16) + (size_t)(kInvSeg / kInvRun) * 128);
+    return sizeof(double) * ((size_t)kInvSeg * w + 2 * (size_t)(kInvSeg + 16) + (size_t)(kInvSeg / kRun) * 128);
 }
 
 }  // namespace
@@ -730,34 +748,53 @@ int fft_inverse(rexi_plan* pl, const LegTables& t, double* grid, int nf, const d
     return REXI_OK;
 }
 
-// EO (C columns) -> spec [C/2][nspec(t.T)], in launches of at most 32 columns
+// EO (C columns) -> spec [C/2][nspec(t.T)], in launches of at most 32 columns;
+// each wave takes half of a launch's four-column groups
 int leg_forward(rexi_plan* pl, const LegTables& t, double* spec, int C, hipStream_t s) {
     const double2* coef = reinterpret_cast<const double2*>(t.d_lcoef);
     for (int c0 = 0; c0 < C; c0 += 32) {
         const int w = std::min(32, C - c0);
-        hipLaunchKernelGGL(k_legendre_forward, dim3(t.ntiles_f), dim3(256), 0, s, (const LegRun*)t.d_tiles_f,
-                           t.d_restart, coef, pl->d_mu, pl->d_four, spec, t.T, pl->nhalf, C, c0, w);
+        const int nh = ((w + 3) / 4 + 1) / 2;  // column groups per wave, 1..4
+        const dim3 g(t.ntiles_f), b(256);
+        const LegRun* rl = (const LegRun*)t.d_tiles_f;
+#define REXI_FWD(NH_)                                                                                           \
+    if (nh == NH_)                                                                                              \
+    hipLaunchKernelGGL(k_legendre_forward<NH_>, g, b, 0, s, rl, t.d_restart, coef, pl->d_mu, pl->d_four, spec, \
+                       t.T, pl->nhalf, C, c0, w)
+        REXI_FWD(1);
+        REXI_FWD(2);
+        REXI_FWD(3);
+        REXI_FWD(4);
+#undef REXI_FWD
         REXI_HIP(hipGetLastError());
     }
     return REXI_OK;
 }
 
 // spec [C/2][nspec(t.T)] -> partial slots of Fw (C columns), in launches of
-// at most 32 columns
+// at most 32 columns (up to eight four-column groups)
 int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hipStream_t s) {
     const int H = pl->nhalf;
     const double2* coef = reinterpret_cast<const double2*>(t.d_lcoef);
     for (int c0 = 0; c0 < C; c0 += 32) {
         const int w = std::min(32, C - c0);
+        const int ng = (w + 3) / 4;
         const size_t li = inverse_lds(w);
         const LegWork* wl = (const LegWork*)t.d_tiles_i;
         const dim3 g(t.ntiles_i), b(256);
-        if (w > 16)
-            hipLaunchKernelGGL(k_legendre_inverse<2>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec,
-                               pl->d_four, t.T, pl->nlat, H, C, c0, w);
-        else
-            hipLaunchKernelGGL(k_legendre_inverse<1>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec,
-                               pl->d_four, t.T, pl->nlat, H, C, c0, w);
+#define REXI_INV(NG_)                                                                                              \
+    if (ng == NG_)                                                                                                 \
+    hipLaunchKernelGGL(k_legendre_inverse<NG_>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec, pl->d_four, \
+                       t.T, pl->nlat, H, C, c0, w)
+        REXI_INV(1);
+        REXI_INV(2);
+        REXI_INV(3);
+        REXI_INV(4);
+        REXI_INV(5);
+        REXI_INV(6);
+        REXI_INV(7);
+        REXI_INV(8);
+#undef REXI_INV
         REXI_HIP(hipGetLastError());
     }
     return REXI_OK;

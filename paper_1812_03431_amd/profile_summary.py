@@ -8,6 +8,9 @@ traffic:  two runs of ``bench.py --copy-calibration`` under ``rocprofv3 --pmc
           scaled by what it reads for an elementwise kernel that reads and
           writes 1 GiB (torch.mul on 2^27 doubles; the largest such
           dispatch of the run).
+sh:       a kernel-trace run and one SQ counter run of ``profile_sh`` -> per
+          transform kernel: duration, algorithmic TF/s of the Legendre
+          kernels, MFMA work executed and MFMA-pipe busy fraction.
 counters: one run under ``rocprofv3 --pmc`` with SQ counters -> per class and
           per step: VALU wave-instructions, FP64 flops executed
           (SQ_INSTS_VALU_FLOPS_FP64 counts the flops of one lane per
@@ -205,6 +208,56 @@ def stats(stats_csv, trace_csv, schedule, workload, command, events_ms):
     return "\n".join(lines) + "\n"
 
 
+# flops of one MFMA wave-instruction of the Legendre kernels
+# (v_mfma_f64_4x4x4f64: four blocks of 4 x 4 x 4 multiply-adds)
+LEGENDRE_MFMA_FLOPS = 4 * 4 * 4 * 4 * 2
+SH_KERNELS = ("k_fft_forward", "k_legendre_forward", "k_legendre_inverse", "k_fft_inverse")
+
+
+def sh(stats_csv, pmc_csv, title, commands, T, nlat, fields, peak=78.6):
+    """Text summary of the transform kernels: durations (kernel trace) and,
+    per dispatch, MFMA instructions, MFMA-pipe busy fraction, waves, VALU
+    instructions per wave and LDS bank-conflict cycles (one counter run)."""
+    nspec = (T + 1) * (T + 2) // 2
+    alg = 2.0 * (nlat // 2) * (2 * fields) * nspec
+    short = lambda n: next((k for k in SH_KERNELS if k in n), None)
+    dur = {}
+    for r in rows(stats_csv):
+        k = short(r["Name"])
+        if k:
+            dur[k] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3)
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for r in rows(pmc_csv):
+        k = short(r["Kernel_Name"])
+        if k:
+            per[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k].add(r["Dispatch_Id"])
+    lines = [f"# {title}", "# commands (on the GPU box, from /tmp with TMPDIR=/tmp and PYTHONPATH=<repo>):"]
+    lines += [f"#   {c}" for c in commands]
+    lines += [f"# algorithmic Legendre flops per launch 2 (nlat/2) (2B) nspec = {alg:.4g}; FP64 matrix peak {peak} TFLOP/s",
+              "# MFMA pipe busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs); executed = "
+              f"SQ_INSTS_MFMA x {LEGENDRE_MFMA_FLOPS} flop (v_mfma_f64_4x4x4f64)",
+              "# summary: python -m paper_1812_03431_amd.profile_summary sh (this file's arguments)", "",
+              f"{'kernel':22s} {'calls':>5s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'alg_TF':>7s} {'frac':>6s} "
+              f"{'exec_MFLOP':>10s} {'mfma_busy':>9s} {'waves':>6s} {'valu/wave':>9s} {'lds_conf':>9s}"]
+    for k in SH_KERNELS:
+        if k not in dur:
+            continue
+        n, avg, lo, hi = dur[k]
+        c = per.get(k, {})
+        nd = max(1, len(disp.get(k, ())))
+        leg = "legendre" in k
+        tf = alg / (avg * 1e-6) / 1e12 if leg else float("nan")
+        busy = (c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (1024.0 * c["GRBM_GUI_ACTIVE"] / 8.0)
+                if c.get("GRBM_GUI_ACTIVE") else float("nan"))
+        waves = c.get("SQ_WAVES", 0.0) / nd
+        lines.append(f"{k:22s} {n:5d} {avg:8.2f} {lo:8.2f} {hi:8.2f} {tf:7.2f} {tf / peak:6.1%} "
+                     f"{c.get('SQ_INSTS_MFMA', 0.0) / nd * LEGENDRE_MFMA_FLOPS / 1e6:10.1f} {busy:9.1%} {waves:6.0f} "
+                     f"{c.get('SQ_INSTS_VALU', 0.0) / nd / max(1.0, waves):9.0f} {c.get('SQ_LDS_BANK_CONFLICT', 0.0) / nd:9.0f}")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -225,7 +278,20 @@ def main():
         p.add_argument("--schedule", type=int, required=True)
         p.add_argument("--workload", default="t256_fwd_adj")
         p.add_argument("--command", action="append", default=[], help="the rocprofv3 command lines (recorded)")
+    x = sub.add_parser("sh")
+    x.add_argument("--stats", required=True)
+    x.add_argument("--pmc", required=True)
+    x.add_argument("--out", required=True)
+    x.add_argument("--title", required=True)
+    x.add_argument("--T", type=int, required=True)
+    x.add_argument("--nlat", type=int, required=True)
+    x.add_argument("--fields", type=int, required=True)
+    x.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
+    if a.what == "sh":
+        with open(a.out, "w") as f:
+            f.write(sh(a.stats, a.pmc, a.title, a.command, a.T, a.nlat, a.fields))
+        return
     if a.what == "stats":
         with open(a.out, "w") as f:
             f.write(stats(a.stats, a.trace, a.schedule, a.workload, " ".join(a.command), a.events_ms))

@@ -63,6 +63,7 @@ def load_library():
         "rexi_plan_get_schedule": [P, c_int, POINTER(c_int)],
         "rexi_solve_variants": [c_int, c_int, P, P, P, POINTER(c_int)],
         "rexi_plan_schedule_classes": [P, c_int, c_int, c_int, P, P, P, POINTER(c_int)],
+        "rexi_plan_schedule_name": [P, c_int, c_int, ctypes.c_char_p, c_int],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -284,6 +285,13 @@ class Plan:
         of schedule ``index`` (-1: the per-term schedule)."""
         return _int_triples(lambda cap, a, b, c, n: self._lib.rexi_plan_schedule_classes(
             self._h, S, index, cap, a, b, c, n), "rexi_plan_schedule_classes")
+
+    def schedule_name(self, S: int, index: int) -> str:
+        """Name of schedule ``index`` (-1: the per-term schedule): tile policy,
+        item count, persistent or not, states sharing factorisations."""
+        buf = ctypes.create_string_buffer(128)
+        _check(self._lib.rexi_plan_schedule_name(self._h, S, index, buf, len(buf)), "rexi_plan_schedule_name")
+        return buf.value.decode()
 
     def set_schedule(self, S: int, index: int):
         _check(self._lib.rexi_plan_set_schedule(self._h, S, index, None), "rexi_plan_set_schedule")

@@ -80,7 +80,11 @@ def _every_schedule(plan, S, u0, want, want_a, T, tag, torch_dev):
     for i in range(plan.schedule_count(S)):
         plan.set_schedule(S, i)
         classes = plan.schedule_classes(S, i)
-        print(f"  {tag} schedule {i} {classes}", flush=True)
+        name = plan.schedule_name(S, i)
+        print(f"  {tag} schedule {i} {name} {classes}", flush=True)
+        # the name says when states share factorisations, and in which classes
+        shared = [c[2] > 1 for c in classes]
+        assert ("_shared" in name or "_mixed" in name) == any(shared), (name, classes)
         got = plan.step(_gpu(u0, torch_dev)).cpu().numpy()
         assert_parity(got, want, T, what=f"{tag} schedule {i} {classes}")
         got_a = plan.step_adjoint(_gpu(u0, torch_dev)).cpu().numpy()
