@@ -50,7 +50,8 @@ std::vector<double> legendre_restarts(int T, int run, const std::vector<double>&
 // plan's truncation): restart rows, recurrence coefficients and work lists.
 struct LegTables {
     int T = 0;
-    double* d_restart = nullptr;  // [row][2][nhalf]
+    double* d_restart = nullptr;  // [row][2][nhalf], rows every 32 degrees
+    double* d_restart8 = nullptr; // [row][2][nhalf], rows every 8 degrees (grids of <= 128 northern latitudes; inverse)
     double* d_lcoef = nullptr;    // [nspec(T)][2]
     void* d_tiles_f = nullptr;    // forward runs
     void* d_tiles_i = nullptr;    // inverse work

@@ -428,22 +428,25 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
 // Inverse: over one degree segment of order m, Fw[slot][j] = Fe + Fo,
 // Fw[slot][j'] = Fe - Fo with Fe / Fo the sums of P_n^m(mu_j) S_n over the
 // segment's n with n - m even / odd (the inverse FFT adds the segments of an
-// order).  A segment is four kRun-degree runs; a workgroup takes up to four
+// order).  A segment is four parts (kRun degrees each, or with restart rows
+// every 8 degrees the shortest multiple of 8 that covers the segment in
+// four); a workgroup takes up to four
 // 16-latitude tiles (one wave each) and stages in LDS the segment's spectral
 // block Sm [Ls][C], its coefficient column and the exact restart values of
-// its 64 latitudes at the start of each run.  The runs are the k index of the
-// four-block MFMA: lane 16 kq + i (i < 16) runs the recurrence of latitude i
-// over run kq from its own restart values, so no two lanes repeat a
-// recurrence and no lane selects values, and per k-step s it holds
-// A_even = P at run degree 2 s and A_odd = P at 2 s + 1 (run starts are a
-// multiple of kRun from m, so the parity of n - m is that of the run degree).
+// its 64 latitudes at the start of each part.  The parts are the k index of
+// the four-block MFMA: lane 16 kq + i (i < 16) runs the recurrence of
+// latitude i over part kq from its own restart values, so no two lanes repeat
+// a recurrence and no lane selects values, and per k-step s it holds
+// A_even = P at part degree 2 s and A_odd = P at 2 s + 1 (parts start an even
+// number of degrees from m, so the parity of n - m is that of the part
+// degree).
 // In the MFMA that lane is A[i & 3][kq] of block i >> 2: latitude i of the
 // tile.  The blocks share B, the segment's coefficients
-// S[32 kq + 2 s (+1)][4 g + (lane & 3)] of column group g, and the result
+// S[Lp kq + 2 s (+1)][4 g + (lane & 3)] of column group g, and the result
 // D[q][p] of lane 16 q + 4 b + p is latitude 4 b + q, column 4 g + p.
 // Degrees past the segment need no checks: their coefficients are zero, so P
-// is zero there, and the B reads are clamped into the block; runs that start
-// past the order's last degree have zero restart values.
+// is zero there, and the B reads are clamped into the block; parts that start
+// past the segment have zero restart values.
 
 // Stage the spectral block of degrees m + n0 .. m + n0 + Ls - 1 ([Ls][C],
 // columns c_off..) and its coefficient column ([kInvSeg + 16], cf[k] for
@@ -475,13 +478,16 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
                                                           const double* __restrict__ mu,
                                                           const double* __restrict__ spec,
                                                           double* __restrict__ Fw, int T, int nlat, int H, int Cs,
-                                                          int c_off, int C) {
+                                                          int c_off, int C, int rr) {
     extern __shared__ double lds[];
     const LegWork wk = work[blockIdx.x];
     if (wk.m < 0) return;  // padding slot of the XCD-ordered list
     const int m = wk.m;
     const int Ls = min(kInvSeg, T + 1 - m - wk.n0);  // degrees of this segment
-    const int nr = (Ls + kRun - 1) / kRun;             // runs of this segment that hold degrees
+    // part length: restart rows every rr degrees (8 or kRun); with rows every
+    // 8 degrees the four parts shrink with the segment (the shortest multiple
+    // of 8 that covers it), so short segments idle fewer MFMA k slots
+    const int Lp = (rr == 8) ? 8 * ((Ls + 31) / 32) : kRun;
     double* Sm = lds;                                        // [Ls][C]
     double2* cf = reinterpret_cast<double2*>(lds + Ls * C);  // [kInvSeg + 16] (Ls * C is even: C is)
     double* Rs = lds + Ls * C + 2 * (kInvSeg + 16);          // [4][2][64]
@@ -489,7 +495,7 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     const int jw = wk.t0 * 16;  // first latitude of the workgroup
     for (int k = threadIdx.x; k < 4 * 128; k += blockDim.x) {
         const int r = k >> 7, w = (k >> 6) & 1, j = min(jw + (k & 63), H - 1);
-        Rs[k] = (r < nr) ? restart[((long long)(wk.run0 + r) * 2 + w) * H + j] : 0.0;
+        Rs[k] = (r * Lp < Ls) ? restart[((long long)(wk.run0 + r * (Lp / rr)) * 2 + w) * H + j] : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -498,16 +504,16 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     const int i = lane & 15, kq = lane >> 4, p = lane & 3;
     const int j = t * 16 + i;
     const double x = (j < H) ? mu[j] : 0.0;
-    const int rb = kq * kRun;  // first segment degree of this lane's run
+    const int rb = kq * Lp;  // first segment degree of this lane's part
     double pv = Rs[(kq * 2) * 64 + wave * 16 + i];
     double cu = Rs[(kq * 2 + 1) * 64 + wave * 16 + i];
     double ae[NG], ao[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) ae[g] = ao[g] = 0.0;
 #pragma unroll 4
-    for (int s = 0; s < kRun / 2; ++s) {
-        const int d = rb + 2 * s;                          // even run degree (segment-relative)
-        const double2 c1 = cf[d + 1], c2 = cf[d + 2];      // d + 2 <= kInvSeg
+    for (int s = 0; s < Lp / 2; ++s) {
+        const int d = rb + 2 * s;                          // even part degree (segment-relative)
+        const double2 c1 = cf[d + 1], c2 = cf[d + 2];      // d + 2 <= 4 Lp <= kInvSeg
         const double* be = Sm + min(d, Ls - 1) * C + p;
         const double* bo = Sm + min(d + 1, Ls - 1) * C + p;
         const double a_e = cu;
@@ -617,6 +623,11 @@ __global__ void __launch_bounds__(256) k_uv_spec_to_vd(const double2* __restrict
 
 // Inverse LDS: a segment's block [kInvSeg][w], coefficient column and restart
 // values (2 x 64 latitudes per run).
+// Restart rows every 8 degrees (besides every kRun) for grids of at most 128
+// northern latitudes, where the table stays small (9 MB at T256): the
+// inverse's four parts then shrink with short segments.
+bool restart8_rows(int H) { return H <= 128; }
+
 size_t inverse_lds(int w) {
     return sizeof(double) * ((size_t)kInvSeg * w + 2 * (size_t)(kInvSeg + 16) + (size_t)(kInvSeg / kRun) * 128);
 }
@@ -635,9 +646,12 @@ int device_alloc(void** p, size_t bytes) {
 // degrees 0..Tt over orders m <= the plan's T.
 int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& north) {
     const int T = pl->T, H = pl->nhalf;
-    std::vector<int> run_base;
+    std::vector<int> run_base, run_base8;
     std::vector<double> restart = legendre_restarts(Tt, kRun, north, run_base);
     std::vector<double> lcoef = legendre_coefs(Tt);
+    const bool reg = restart8_rows(H);
+    std::vector<double> restart8;
+    if (reg) restart8 = legendre_restarts(Tt, 8, north, run_base8);
     // forward: one workgroup per kFwdGroup consecutive 32-degree runs of an
     // order.  Workgroups go to the eight
     // XCDs round-robin by index, so slot s is filled from the queue of XCD
@@ -682,7 +696,8 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
                 if ((m + n0 + kInvSeg - 1 <= Tt) != (full == 1)) continue;
                 std::vector<LegWork>& dst = qi[kseg++ % kXcd];
                 for (int t0 = 0; t0 < nl; t0 += 4)
-                    dst.push_back(LegWork{m, t0, std::min(nl, t0 + 4), run_base[m] + n0 / kRun, n0,
+                    dst.push_back(LegWork{m, t0, std::min(nl, t0 + 4),
+                                          reg ? run_base8[m] + n0 / 8 : run_base[m] + n0 / kRun, n0,
                                           seg[m] + n0 / kInvSeg});
             }
     size_t qimax = 0;
@@ -693,12 +708,15 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
     t.nslots = seg[T + 1];
     t.T = Tt;
     int rc = device_alloc((void**)&t.d_restart, restart.size() * sizeof(double));
+    if (!rc && reg) rc = device_alloc((void**)&t.d_restart8, restart8.size() * sizeof(double));
     if (!rc) rc = device_alloc((void**)&t.d_lcoef, lcoef.size() * sizeof(double));
     if (!rc) rc = device_alloc((void**)&t.d_tiles_f, tf.size() * sizeof(LegRun));
     if (!rc) rc = device_alloc((void**)&t.d_tiles_i, ti.size() * sizeof(LegWork));
     if (!rc) rc = device_alloc((void**)&t.d_seg, seg.size() * sizeof(int));
     if (rc) return rc;
     REXI_HIP(hipMemcpy(t.d_restart, restart.data(), restart.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (reg)
+        REXI_HIP(hipMemcpy(t.d_restart8, restart8.data(), restart8.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(t.d_lcoef, lcoef.data(), lcoef.size() * sizeof(double), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(t.d_tiles_f, tf.data(), tf.size() * sizeof(LegRun), hipMemcpyHostToDevice));
     REXI_HIP(hipMemcpy(t.d_tiles_i, ti.data(), ti.size() * sizeof(LegWork), hipMemcpyHostToDevice));
@@ -709,7 +727,7 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
 }
 
 void leg_release(LegTables& t) {
-    void* ptrs[] = {t.d_restart, t.d_lcoef, t.d_tiles_f, t.d_tiles_i, t.d_seg};
+    void* ptrs[] = {t.d_restart, t.d_restart8, t.d_lcoef, t.d_tiles_f, t.d_tiles_i, t.d_seg};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     t = LegTables{};
@@ -782,10 +800,13 @@ int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hi
         const size_t li = inverse_lds(w);
         const LegWork* wl = (const LegWork*)t.d_tiles_i;
         const dim3 g(t.ntiles_i), b(256);
-#define REXI_INV(NG_)                                                                                              \
-    if (ng == NG_)                                                                                                 \
-    hipLaunchKernelGGL(k_legendre_inverse<NG_>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec, pl->d_four, \
-                       t.T, pl->nlat, H, C, c0, w)
+        const bool reg = restart8_rows(H);  // the plan holds restart rows every 8 degrees
+        const double* rst = reg ? t.d_restart8 : t.d_restart;
+        const int rr = reg ? 8 : kRun;
+#define REXI_INV(NG_)                                                                                        \
+    if (ng == NG_)                                                                                           \
+    hipLaunchKernelGGL(k_legendre_inverse<NG_>, g, b, li, s, wl, rst, coef, pl->d_mu, spec, pl->d_four, t.T, \
+                       pl->nlat, H, C, c0, w, rr)
         REXI_INV(1);
         REXI_INV(2);
         REXI_INV(3);
