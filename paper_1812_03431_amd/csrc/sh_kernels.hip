@@ -545,6 +545,110 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     }
 }
 
+// Inverse for grids of more than 128 northern latitudes, on the 16x16x4
+// shape (measured faster there: 674 against 1124 us at T1023 on 2048 x 1024
+// with 16 fields; the four-block kernel's replicated operand reads, NG per
+// parity per k-step, load the LDS more where the column groups are many).  The
+// k index is four consecutive degrees: lanes (i = lane & 15, kq = lane >> 4)
+// run the recurrence of latitude i in registers (the four kq lanes alike,
+// restarted every kSeqRun degrees) and keep what their MFMA fragment needs:
+// per k-step of 8 degrees base .. base + 7, A_even = P_{base + 2 kq},
+// A_odd = P_{base + 2 kq + 1}; B is the spectral block of column tile
+// (16 columns) and k; accumulator register q of lane l holds latitude row
+// 4 q + l/16 of the tile and column l % 16.  Same segments, staging, slots and
+// streaming stores as k_legendre_inverse.
+constexpr int kSeqRun = 64;  // degrees between the sequential inverse's restarts (a multiple of kRun)
+
+template <int NCT>
+__global__ void __launch_bounds__(256) k_legendre_inverse_seq(const LegWork* __restrict__ work,
+                                                          const double* __restrict__ restart,
+                                                          const double2* __restrict__ coef,
+                                                          const double* __restrict__ mu,
+                                                          const double* __restrict__ spec,
+                                                          double* __restrict__ Fw, int T, int nlat, int H, int Cs,
+                                                          int c_off, int C) {
+    extern __shared__ double lds[];
+    const LegWork wk = work[blockIdx.x];
+    if (wk.m < 0) return;  // padding slot of the XCD-ordered list
+    const int m = wk.m;
+    const int Ls = min(kInvSeg, T + 1 - m - wk.n0);  // degrees of this segment
+    const int nr = (Ls + kSeqRun - 1) / kSeqRun;       // restarts of this segment
+    double* Sm = lds;                                        // [Ls][C]
+    double2* cf = reinterpret_cast<double2*>(lds + Ls * C);  // [kInvSeg + 16] (Ls * C is even: C is)
+    double* Rs = lds + Ls * C + 2 * (kInvSeg + 16);          // [nr][2][64]
+    stage_segment(spec_offset(T, m) + wk.n0, nspec_of(T), Ls, C, c_off, spec, coef, Sm, cf);
+    const int jw = wk.t0 * 16;  // first latitude of the workgroup
+    for (int k = threadIdx.x; k < nr * 128; k += blockDim.x) {
+        const int r = k >> 7, w = (k >> 6) & 1, j = min(jw + (k & 63), H - 1);
+        Rs[k] = restart[((long long)(wk.run0 + r * (kSeqRun / kRun)) * 2 + w) * H + j];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = wk.t0 + wave;
+    if (t >= wk.t1) return;  // no latitude tile for this wave (no barrier follows)
+    const int i = lane & 15, kq = lane >> 4;
+    const int j = t * 16 + i;
+    const double x = (j < H) ? mu[j] : 0.0;
+    const int c0 = min(i, C - 1), c1 = min(16 + i, C - 1);
+    v4d ae0 = {0.0, 0.0, 0.0, 0.0}, ao0 = ae0, ae1 = ae0, ao1 = ae0;
+    for (int r = 0; r < nr; ++r) {
+        double pv = Rs[(r * 2) * 64 + wave * 16 + i];
+        double cu = Rs[(r * 2 + 1) * 64 + wave * 16 + i];
+        const int kr = r * kSeqRun;
+#pragma unroll
+        for (int ks = 0; ks < kSeqRun; ks += 8) {
+            const int kb = kr + ks;
+            if (kb >= Ls) break;
+            double2 cv[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) cv[d] = cf[kb + d + 1];  // < Ls + 8 <= kInvSeg + 16
+            const int de = min(kb + 2 * kq, Ls - 1), dd = min(kb + 2 * kq + 1, Ls - 1);
+            const double b0 = Sm[de * C + c0], b1 = Sm[dd * C + c0];
+            const double b2 = Sm[de * C + c1], b3 = Sm[dd * C + c1];
+            double a_e = 0.0, a_o = 0.0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                if ((d & 1) == 0) a_e = (kq == (d >> 1)) ? cu : a_e;
+                else a_o = (kq == (d >> 1)) ? cu : a_o;
+                const double nx = fma(cv[d].x * x, cu, -cv[d].y * pv);
+                pv = cu;
+                cu = nx;
+            }
+            ae0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, b0, ae0, 0, 0, 0);
+            ao0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, b1, ao0, 0, 0, 0);
+            if constexpr (NCT > 1) {
+                ae1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_e, b2, ae1, 0, 0, 0);
+                ao1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a_o, b3, ao1, 0, 0, 0);
+            }
+        }
+    }
+    // accumulator register q of lane l holds D[4 q + l/16][l % 16]: latitude
+    // row 4 q + kq of the tile, column l % 16 of the column tile
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int col = hh * 16 + i;
+        if (hh >= NCT || col >= C) continue;
+        const v4d ae = hh ? ae1 : ae0, ao = hh ? ao1 : ao0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jj = t * 16 + 4 * q + kq;
+            if (jj < H) {
+                // streaming stores: the partials go out while the kernel runs
+                // instead of as dirty L2 lines written back at its end
+                __builtin_nontemporal_store(ae[q] + ao[q], Fw + wk.slot * slot_plane(nlat, Cs) + (long long)jj * Cs + c_off + col);
+                __builtin_nontemporal_store(ae[q] - ao[q],
+                                            Fw + wk.slot * slot_plane(nlat, Cs) + (long long)(nlat - 1 - jj) * Cs + c_off + col);
+            }
+        }
+    }
+}
+
+// Vector transforms (Eq. (1): V = k x grad(psi) + grad(chi), lap psi = zeta,
+// lap chi = delta; Section 3's scaled winds U = u cos(lat), V = v cos(lat)).
+// On degree n, lap = -n(n+1)/a^2, and with eps_n = sqrt((n^2 - m^2)/(4n^2 - 1))
+// the latitude derivative of the orthonormal P_n^m obeys
+//   (1 - mu^2) dP_n^m/dmu = (n + 1) eps_n P_{n-1}^m - n eps_{n+1} P_{n+1}^m,
+
 // Vector transforms (Eq. (1): V = k x grad(psi) + grad(chi), lap psi = zeta,
 // lap chi = delta; Section 3's scaled winds U = u cos(lat), V = v cos(lat)).
 // On degree n, lap = -n(n+1)/a^2, and with eps_n = sqrt((n^2 - m^2)/(4n^2 - 1))
@@ -801,8 +905,18 @@ int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hi
         const LegWork* wl = (const LegWork*)t.d_tiles_i;
         const dim3 g(t.ntiles_i), b(256);
         const bool reg = restart8_rows(H);  // the plan holds restart rows every 8 degrees
-        const double* rst = reg ? t.d_restart8 : t.d_restart;
-        const int rr = reg ? 8 : kRun;
+        if (!reg) {
+            if (w > 16)
+                hipLaunchKernelGGL(k_legendre_inverse_seq<2>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec,
+                                   pl->d_four, t.T, pl->nlat, H, C, c0, w);
+            else
+                hipLaunchKernelGGL(k_legendre_inverse_seq<1>, g, b, li, s, wl, t.d_restart, coef, pl->d_mu, spec,
+                                   pl->d_four, t.T, pl->nlat, H, C, c0, w);
+            REXI_HIP(hipGetLastError());
+            continue;
+        }
+        const double* rst = t.d_restart8;
+        const int rr = 8;
 #define REXI_INV(NG_)                                                                                        \
     if (ng == NG_)                                                                                           \
     hipLaunchKernelGGL(k_legendre_inverse<NG_>, g, b, li, s, wl, rst, coef, pl->d_mu, spec, pl->d_four, t.T, \
