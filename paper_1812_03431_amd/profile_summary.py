@@ -208,10 +208,12 @@ def stats(stats_csv, trace_csv, schedule, workload, command, events_ms):
     return "\n".join(lines) + "\n"
 
 
-# flops of one MFMA wave-instruction of the Legendre kernels
-# (v_mfma_f64_4x4x4f64: four blocks of 4 x 4 x 4 multiply-adds)
-LEGENDRE_MFMA_FLOPS = 4 * 4 * 4 * 4 * 2
-SH_KERNELS = ("k_fft_forward", "k_legendre_forward", "k_legendre_inverse", "k_fft_inverse")
+# flops of one MFMA wave-instruction of each Legendre kernel:
+# v_mfma_f64_4x4x4f64 (four blocks of 4 x 4 x 4 multiply-adds) or, in the
+# inverse for grids of more than 128 northern latitudes, v_mfma_f64_16x16x4f64
+MFMA_FLOPS = {"k_legendre_forward": 4 * 4 * 4 * 4 * 2, "k_legendre_inverse": 4 * 4 * 4 * 4 * 2,
+              "k_legendre_inverse_seq": 16 * 16 * 4 * 2}
+SH_KERNELS = ("k_fft_forward", "k_legendre_forward", "k_legendre_inverse_seq", "k_legendre_inverse", "k_fft_inverse")
 
 
 def sh(stats_csv, pmc_csv, title, commands, T, nlat, fields, peak=78.6):
@@ -237,9 +239,9 @@ def sh(stats_csv, pmc_csv, title, commands, T, nlat, fields, peak=78.6):
     lines += [f"#   {c}" for c in commands]
     lines += [f"# algorithmic Legendre flops per launch 2 (nlat/2) (2B) nspec = {alg:.4g}; FP64 matrix peak {peak} TFLOP/s",
               "# MFMA pipe busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs); executed = "
-              f"SQ_INSTS_MFMA x {LEGENDRE_MFMA_FLOPS} flop (v_mfma_f64_4x4x4f64)",
+              "SQ_INSTS_MFMA x 512 flop (v_mfma_f64_4x4x4f64) or x 2048 (v_mfma_f64_16x16x4f64, k_legendre_inverse_seq)",
               "# summary: python -m paper_1812_03431_amd.profile_summary sh (this file's arguments)", "",
-              f"{'kernel':22s} {'calls':>5s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'alg_TF':>7s} {'frac':>6s} "
+              f"{'kernel':24s} {'calls':>5s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'alg_TF':>7s} {'frac':>6s} "
               f"{'exec_MFLOP':>10s} {'mfma_busy':>9s} {'waves':>6s} {'valu/wave':>9s} {'lds_conf':>9s}"]
     for k in SH_KERNELS:
         if k not in dur:
@@ -252,8 +254,8 @@ def sh(stats_csv, pmc_csv, title, commands, T, nlat, fields, peak=78.6):
         busy = (c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (1024.0 * c["GRBM_GUI_ACTIVE"] / 8.0)
                 if c.get("GRBM_GUI_ACTIVE") else float("nan"))
         waves = c.get("SQ_WAVES", 0.0) / nd
-        lines.append(f"{k:22s} {n:5d} {avg:8.2f} {lo:8.2f} {hi:8.2f} {tf:7.2f} {tf / peak:6.1%} "
-                     f"{c.get('SQ_INSTS_MFMA', 0.0) / nd * LEGENDRE_MFMA_FLOPS / 1e6:10.1f} {busy:9.1%} {waves:6.0f} "
+        lines.append(f"{k:24s} {n:5d} {avg:8.2f} {lo:8.2f} {hi:8.2f} {tf:7.2f} {tf / peak:6.1%} "
+                     f"{c.get('SQ_INSTS_MFMA', 0.0) / nd * MFMA_FLOPS.get(k, 0) / 1e6:10.1f} {busy:9.1%} {waves:6.0f} "
                      f"{c.get('SQ_INSTS_VALU', 0.0) / nd / max(1.0, waves):9.0f} {c.get('SQ_LDS_BANK_CONFLICT', 0.0) / nd:9.0f}")
     return "\n".join(lines) + "\n"
 
