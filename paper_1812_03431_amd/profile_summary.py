@@ -237,7 +237,8 @@ def sh(stats_csv, pmc_csv, title, commands, T, nlat, fields, peak=78.6):
             disp[k].add(r["Dispatch_Id"])
     lines = [f"# {title}", "# commands (on the GPU box, from /tmp with TMPDIR=/tmp and PYTHONPATH=<repo>):"]
     lines += [f"#   {c}" for c in commands]
-    lines += [f"# algorithmic Legendre flops per launch 2 (nlat/2) (2B) nspec = {alg:.4g}; FP64 matrix peak {peak} TFLOP/s",
+    lines += [f"# algorithmic Legendre flops per launch 2 (nlat/2) (2B) nspec = {alg:.4g} (folded: the kernels use the "
+              f"equatorial symmetry; unfolded, 2 nlat (2B) nspec, twice that: frac x 2); FP64 matrix peak {peak} TFLOP/s",
               "# MFMA pipe busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs); executed = "
               "SQ_INSTS_MFMA x 512 flop (v_mfma_f64_4x4x4f64) or x 2048 (v_mfma_f64_16x16x4f64, k_legendre_inverse_seq)",
               "# summary: python -m paper_1812_03431_amd.profile_summary sh (this file's arguments)", "",
