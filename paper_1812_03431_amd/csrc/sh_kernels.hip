@@ -279,7 +279,8 @@ struct LegRun {
     int m, n0, row, nrun;
 };
 struct LegWork {
-    int m, t0, t1, run0;  // order, latitude tiles [t0, t1), restart row of degree m + n0
+    int m, t0, t1, run0;  // order, latitude tiles [t0, t1), restart row of degree m + n0 (the 8-degree table
+                          // on grids of at most 128 northern latitudes, else the 32-degree one)
     int n0, slot;         // first degree (offset from m) of the segment, output slot
 };
 
@@ -428,9 +429,9 @@ __global__ void __launch_bounds__(256) k_legendre_forward(const LegRun* __restri
 // Inverse: over one degree segment of order m, Fw[slot][j] = Fe + Fo,
 // Fw[slot][j'] = Fe - Fo with Fe / Fo the sums of P_n^m(mu_j) S_n over the
 // segment's n with n - m even / odd (the inverse FFT adds the segments of an
-// order).  A segment is four parts (kRun degrees each, or with restart rows
-// every 8 degrees the shortest multiple of 8 that covers the segment in
-// four); a workgroup takes up to four
+// order).  A segment is four parts (the shortest multiple of 8 degrees that
+// covers it in four; restart rows every 8 degrees, grids of at most 128
+// northern latitudes); a workgroup takes up to four
 // 16-latitude tiles (one wave each) and stages in LDS the segment's spectral
 // block Sm [Ls][C], its coefficient column and the exact restart values of
 // its 64 latitudes at the start of each part.  The parts are the k index of
@@ -473,21 +474,21 @@ __device__ __forceinline__ void stage_segment(long long so, long long ns, int Ls
 
 template <int NG>
 __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restrict__ work,
-                                                          const double* __restrict__ restart,
+                                                          const double* __restrict__ restart8,
                                                           const double2* __restrict__ coef,
                                                           const double* __restrict__ mu,
                                                           const double* __restrict__ spec,
                                                           double* __restrict__ Fw, int T, int nlat, int H, int Cs,
-                                                          int c_off, int C, int rr) {
+                                                          int c_off, int C) {
     extern __shared__ double lds[];
     const LegWork wk = work[blockIdx.x];
     if (wk.m < 0) return;  // padding slot of the XCD-ordered list
     const int m = wk.m;
     const int Ls = min(kInvSeg, T + 1 - m - wk.n0);  // degrees of this segment
-    // part length: restart rows every rr degrees (8 or kRun); with rows every
-    // 8 degrees the four parts shrink with the segment (the shortest multiple
-    // of 8 that covers it), so short segments idle fewer MFMA k slots
-    const int Lp = (rr == 8) ? 8 * ((Ls + 31) / 32) : kRun;
+    // part length: the shortest multiple of 8 (the restart rows' spacing)
+    // that covers the segment in four parts, so short segments idle few MFMA
+    // k slots
+    const int Lp = 8 * ((Ls + 31) / 32);
     double* Sm = lds;                                        // [Ls][C]
     double2* cf = reinterpret_cast<double2*>(lds + Ls * C);  // [kInvSeg + 16] (Ls * C is even: C is)
     double* Rs = lds + Ls * C + 2 * (kInvSeg + 16);          // [4][2][64]
@@ -495,7 +496,7 @@ __global__ void __launch_bounds__(256) k_legendre_inverse(const LegWork* __restr
     const int jw = wk.t0 * 16;  // first latitude of the workgroup
     for (int k = threadIdx.x; k < 4 * 128; k += blockDim.x) {
         const int r = k >> 7, w = (k >> 6) & 1, j = min(jw + (k & 63), H - 1);
-        Rs[k] = (r * Lp < Ls) ? restart[((long long)(wk.run0 + r * (Lp / rr)) * 2 + w) * H + j] : 0.0;
+        Rs[k] = (r * Lp < Ls) ? restart8[((long long)(wk.run0 + r * (Lp / 8)) * 2 + w) * H + j] : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -915,12 +916,11 @@ int leg_inverse(rexi_plan* pl, const LegTables& t, const double* spec, int C, hi
             REXI_HIP(hipGetLastError());
             continue;
         }
-        const double* rst = t.d_restart8;
-        const int rr = 8;
+
 #define REXI_INV(NG_)                                                                                        \
     if (ng == NG_)                                                                                           \
-    hipLaunchKernelGGL(k_legendre_inverse<NG_>, g, b, li, s, wl, rst, coef, pl->d_mu, spec, pl->d_four, t.T, \
-                       pl->nlat, H, C, c0, w, rr)
+    hipLaunchKernelGGL(k_legendre_inverse<NG_>, g, b, li, s, wl, t.d_restart8, coef, pl->d_mu, spec, pl->d_four, \
+                       t.T, pl->nlat, H, C, c0, w)
         REXI_INV(1);
         REXI_INV(2);
         REXI_INV(3);
