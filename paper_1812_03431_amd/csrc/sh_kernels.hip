@@ -262,10 +262,12 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const double* __restrict__ 
 
 // Legendre contractions with P_n^m generated on the device.  The table
 // itself (34 MB at T256) is never stored: P follows from the three-term
-// recurrence P_n = a_n mu P_{n-1} - b_n P_{n-2}, restarted every kRun degrees
-// from exact host values, which keeps the FP64 recurrence error at a few ulp.
+// recurrence P_n = a_n mu P_{n-1} - b_n P_{n-2}, restarted from exact host
+// values every kRun degrees (and, on grids of at most 128 northern latitudes,
+// also every 8 degrees for the inverse), which keeps the FP64 recurrence
+// error at a few ulp.
 constexpr int kRun = 32;         // degrees per restart row of the table
-constexpr int kInvSeg = 4 * kRun;  // degrees per inverse work item: four runs, the MFMA's k index
+constexpr int kInvSeg = 4 * kRun;  // degrees per inverse work item (at most; four parts)
 constexpr int kFwdDeg = 32;      // degrees per forward run: two 16-row parity tiles
 constexpr int kFwdLat = 128;     // latitudes per generated forward block
 constexpr int kPtPitch = kFwdLat + 1;  // LDS row pitch of the generated tile (odd: spreads banks)
