@@ -314,6 +314,14 @@ def test_argument_errors(torch_dev):
         plan.step(u, out=u)
     with pytest.raises(rexi.RexiError, match="without a grid"):
         rexi.rexi._check(plan._lib.sh_forward(plan._h, None, None, 1, None), "sh_forward")
+    # schedule queries: index range, the per-term schedule before its first use, NULL buffer
+    n = plan.schedule_count(2)
+    assert plan.schedule_name(2, n - 1)
+    with pytest.raises(rexi.RexiError, match="out of range"):
+        plan.schedule_name(2, n)
+    with pytest.raises(rexi.RexiError, match="per-term"):
+        plan.schedule_name(2, -1)
+    assert plan._lib.rexi_plan_schedule_name(plan._h, 2, 0, None, 16) == -1
 
 
 def test_graph_replays_match_direct_launches(torch_dev):
