@@ -177,7 +177,7 @@ def stats(stats_csv, trace_csv, schedule, workload, command, events_ms):
     """Text summary of a kernel-trace run: per-kernel statistics and the span
     of each REXI step (first solve class start to its reduction's end)."""
     lines = [f"# rocprofv3 kernel statistics: {workload} benchmark job (bench.py), schedule {schedule}",
-             "# command (on the GPU box, from /tmp with TMPDIR=/tmp):", f"#   {command}",
+             "# command (on one MI355X, from /tmp with TMPDIR=/tmp):", f"#   {command}",
              "# one REXI step = one captured graph: a k_solve launch per tile class "
              "(template <elements per lane, per-term, move kind, waves, states per item>) and k_reduce;",
              "# k_solve<.., true, .., 1, 1> are the per-term comparison launches (one per pole and class).",
@@ -235,7 +235,7 @@ def sh(stats_csv, pmc_csv, title, commands, T, nlat, fields, peak=78.6):
         if k:
             per[k][r["Counter_Name"]] += float(r["Counter_Value"])
             disp[k].add(r["Dispatch_Id"])
-    lines = [f"# {title}", "# commands (on the GPU box, from /tmp with TMPDIR=/tmp and PYTHONPATH=<repo>):"]
+    lines = [f"# {title}", "# commands (on one MI355X, from /tmp with TMPDIR=/tmp and PYTHONPATH=<repo>):"]
     lines += [f"#   {c}" for c in commands]
     lines += [f"# algorithmic Legendre flops per launch 2 (nlat/2) (2B) nspec = {alg:.4g} (folded: the kernels use the "
               f"equatorial symmetry; unfolded, 2 nlat (2B) nspec, twice that: frac x 2); FP64 matrix peak {peak} TFLOP/s",
