@@ -146,18 +146,30 @@ def traffic(fetch_csv, write_csv, schedule, workload, commands, earlier=()):
     return solve, per_term
 
 
-def counters(csv_path, schedule, workload, commands, steps_note):
+# per-wave shares of a wave's lifetime (SQ_WAVE_CYCLES), where the counters
+# were taken: issuing any instruction, issuing VALU instructions, waiting at
+# s_waitcnt, waiting for an instruction's operands (dependencies)
+STALL_SHARES = {"active_any": "SQ_ACTIVE_INST_ANY", "active_valu": "SQ_ACTIVE_INST_VALU",
+                "wait_any": "SQ_WAIT_ANY", "wait_inst_any": "SQ_WAIT_INST_ANY"}
+
+
+def counters(csv_paths, schedule, workload, commands, steps_note, clock_ghz=2.4, simds=1024):
+    """Per class (mean per dispatch) and per step sums of the counters of one
+    or more rocprofv3 --pmc runs (one CSV each)."""
+    if isinstance(csv_paths, str):
+        csv_paths = [csv_paths]
     per = collections.defaultdict(lambda: collections.defaultdict(list))
-    for r in rows(csv_path):
-        k, c = class_of(r["Kernel_Name"])
-        if k != "batched":
-            continue
-        per[c][(r["Counter_Name"], r["Dispatch_Id"])].append(float(r["Counter_Value"]))
+    for run, path in enumerate(csv_paths):
+        for r in rows(path):
+            k, c = class_of(r["Kernel_Name"])
+            if k != "batched":
+                continue
+            per[c][(r["Counter_Name"], run, r["Dispatch_Id"])].append(float(r["Counter_Value"]))
     per_class = {}
     step = collections.Counter()
     for c, d in per.items():
         acc = collections.defaultdict(list)
-        for (name, _), v in d.items():
+        for (name, _run, _disp), v in d.items():
             acc[name].append(sum(v))
         mean = {name: sum(v) / len(v) for name, v in acc.items()}
         mean["dispatches"] = max(len(v) for v in acc.values())
@@ -170,6 +182,21 @@ def counters(csv_path, schedule, workload, commands, steps_note):
            "per_class_mean_per_dispatch": per_class, "per_step": dict(step), "note": steps_note}
     if "SQ_INSTS_VALU_FLOPS_FP64" in step:
         out["executed_fp64_flops_per_step"] = 64.0 * step["SQ_INSTS_VALU_FLOPS_FP64"]
+    if "SQ_WAVE_CYCLES" in step:
+        shares = {}
+        for c, m in per_class.items():
+            wc = m.get("SQ_WAVE_CYCLES", 0.0)
+            if wc > 0:
+                shares[c] = {k: m[v] / wc for k, v in STALL_SHARES.items() if v in m}
+        out["stall_shares_per_class"] = shares
+        # SQ_WAVE_CYCLES counts in units of four cycles
+        out["wave_lifetime_over_simds_ms"] = 4.0 * step["SQ_WAVE_CYCLES"] / simds / (clock_ghz * 1e9) * 1e3
+        out["wave_lifetime_note"] = (f"summed wave lifetimes of one step's solve class launches and reduction (4 x SQ_WAVE_CYCLES) "
+                                     f"over {simds} SIMDs at {clock_ghz} GHz")
+    if "SQC_ICACHE_MISSES" in step and step.get("SQC_ICACHE_HITS"):
+        out["icache_miss_per_hit"] = step["SQC_ICACHE_MISSES"] / step["SQC_ICACHE_HITS"]
+    if "SQ_LDS_BANK_CONFLICT" in step and step.get("SQ_LDS_IDX_ACTIVE"):
+        out["lds_bank_conflict_share"] = step["SQ_LDS_BANK_CONFLICT"] / step["SQ_LDS_IDX_ACTIVE"]
     return out
 
 
@@ -275,7 +302,7 @@ def main():
     t.add_argument("--out-solve", required=True)
     t.add_argument("--out-per-term", required=True)
     c = sub.add_parser("counters")
-    c.add_argument("--csv", required=True)
+    c.add_argument("--csv", required=True, action="append", help="one per counter run")
     c.add_argument("--out", required=True)
     for p in (t, c, k):
         p.add_argument("--schedule", type=int, required=True)

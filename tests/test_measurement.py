@@ -108,3 +108,26 @@ def test_sh_summary_counts_each_kernel_shape(tmp_path):
     # executed MFMA work: 512 flops per four-block instruction, 2048 per 16x16x4 one
     assert float(lines["k_legendre_forward"][7]) == pytest.approx(1.0e6 * 512 / 1e6)
     assert float(lines["k_legendre_inverse_seq"][7]) == pytest.approx(1.0e6 * 2048 / 1e6)
+
+
+def test_counter_summary_stall_shares(tmp_path):
+    from paper_1812_03431_amd import profile_summary as ps
+    solve = "void rexi::k_solve<12, false, 1, 4, 4>(SolveArgs, int, int, int*)"
+    p1 = [{"Dispatch_Id": d, "Kernel_Name": solve, "Counter_Name": n, "Counter_Value": v}
+          for d in (1, 2) for n, v in (("SQ_WAVE_CYCLES", 1000.0), ("SQ_ACTIVE_INST_VALU", 700.0),
+                                       ("SQ_WAIT_ANY", 200.0), ("SQ_WAIT_INST_ANY", 10.0))]
+    p2 = [{"Dispatch_Id": d, "Kernel_Name": solve, "Counter_Name": n, "Counter_Value": v}
+          for d in (7, 8) for n, v in (("SQC_ICACHE_HITS", 1.0e4), ("SQC_ICACHE_MISSES", 1.0),
+                                       ("SQ_LDS_BANK_CONFLICT", 6.0), ("SQ_LDS_IDX_ACTIVE", 100.0))]
+    f1, f2 = tmp_path / "p1.csv", tmp_path / "p2.csv"
+    _write(f1, PMC_HEADER, p1)
+    _write(f2, PMC_HEADER, p2)
+    out = ps.counters([str(f1), str(f2)], 70, "t", ["c1", "c2"], "note", clock_ghz=2.0, simds=4)
+    sh = out["stall_shares_per_class"]["k_solve<12, false, 1, 4, 4>"]
+    assert sh["active_valu"] == pytest.approx(0.7) and sh["wait_any"] == pytest.approx(0.2)
+    assert sh["wait_inst_any"] == pytest.approx(0.01)
+    # mean per dispatch; 4 cycles per count; over 4 SIMDs at 2 GHz
+    assert out["wave_lifetime_over_simds_ms"] == pytest.approx(4.0 * 1000.0 / 4 / 2.0e9 * 1e3)
+    assert out["icache_miss_per_hit"] == pytest.approx(1e-4)
+    assert out["lds_bank_conflict_share"] == pytest.approx(0.06)
+    assert out["per_class_mean_per_dispatch"]["k_solve<12, false, 1, 4, 4>"]["dispatches"] == 2
