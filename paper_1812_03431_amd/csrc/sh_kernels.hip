@@ -778,6 +778,10 @@ int leg_build(rexi_plan* pl, LegTables& t, int Tt, const std::vector<double>& no
             q[m % kXcd].push_back(LegRun{m, m + kFwdDeg * r, run_base[m] + r * (kFwdDeg / kRun),
                                          std::min(kFwdGroup, nr - r)});
     }
+    // within a queue, two-run items before one-run items (the longest
+    // orders still first among equals): the short items fill in at the end
+    for (auto& v : q)
+        std::stable_sort(v.begin(), v.end(), [](const LegRun& a, const LegRun& b) { return a.nrun > b.nrun; });
     size_t qmax = 0;
     for (auto& v : q) qmax = std::max(qmax, v.size());
     std::vector<LegRun> tf;
