@@ -11,11 +11,13 @@ traffic:  two runs of ``bench.py --copy-calibration`` under ``rocprofv3 --pmc
 sh:       a kernel-trace run and one SQ counter run of ``profile_sh`` -> per
           transform kernel: duration, algorithmic TF/s of the Legendre
           kernels, MFMA work executed and MFMA-pipe busy fraction.
-counters: one run under ``rocprofv3 --pmc`` with SQ counters -> per class and
-          per step: VALU wave-instructions, FP64 flops executed
+counters: one or more runs under ``rocprofv3 --pmc`` with SQ counters -> per
+          class and per step: VALU wave-instructions, FP64 flops executed
           (SQ_INSTS_VALU_FLOPS_FP64 counts the flops of one lane per
-          wave-instruction, so a step executes 64 times its sum), and the
-          other counters given.
+          wave-instruction, so a step executes 64 times its sum), the other
+          counters given and, where they were taken, each class's shares of
+          wave lifetime (issuing, waiting at s_waitcnt, waiting for operands),
+          instruction-cache misses per hit and the LDS bank-conflict share.
 
 Writes JSON keyed by the solve kernel source's hash (bench.py reports a
 summary only while the hash matches the source).
