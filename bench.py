@@ -104,9 +104,11 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def load_summary(name, digest):
+def load_summary(name, digest, schedule_name=None):
     """A committed counter summary from profiles/, if it was taken on the
-    current solve kernel source; otherwise None."""
+    current solve kernel source and, where a schedule is given, on that
+    schedule (matched by name: indices move when the candidate list
+    changes); otherwise None."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
@@ -114,6 +116,8 @@ def load_summary(name, digest):
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != digest:
+        return None
+    if schedule_name is not None and d.get("schedule_name") != schedule_name:
         return None
     return d
 
@@ -394,10 +398,10 @@ def main():
     achieved = fl / avg_solve_s / 1e12
     fl_thomas = solve_flops_thomas(N, T, S)
     digest = kernel_source_digest()
-    tr = load_summary("k_solve_t256_fwd_adj_traffic.json", digest)
+    tr = load_summary("k_solve_t256_fwd_adj_traffic.json", digest, sched_name)
     traffic = tr.get("traffic_bytes_per_launch") if tr else None
     state_bytes = 2.0 * S * 3 * plan.nspec * 16       # state in and out of one step
-    ctr = load_summary("k_solve_t256_fwd_adj_counters.json", digest)
+    ctr = load_summary("k_solve_t256_fwd_adj_counters.json", digest, sched_name)
     pt = load_summary("per_term_t256_traffic.json", digest)
     per_term_hbm = None
     if pt:

@@ -313,7 +313,10 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
     }
     std::vector<Schedule>& c = pl->sched[S];
     if (c.empty()) {
-        const long long tg[] = {2048, 4096, 8192};
+        // item targets: ~2816 measured fastest at T256 (four states per
+        // item, concurrent classes), by 3% over ~4096, with ~2048 and ~3072
+        // on either side slower
+        const long long tg[] = {2048, 2816, 4096, 8192};
         // states per item (see build_schedule): one (each state factorises
         // its own poles), and for an even number of states up to four sharing
         // each factorisation, in every tile class or in some
@@ -336,9 +339,9 @@ int schedules_for(rexi_plan* pl, int S, std::vector<Schedule>** out) {
                     if (sc.persistent) sc.name = "persistent_" + sc.name;
                     rc = ensure_part(pl, sc.part_size);
                     if (rc) { free_schedule(sc); return rc; }
-                    // until autotuned: "fine", ~4096 items, one launch per item,
+                    // until autotuned: "fine", ~2816 items, one launch per item,
                     // states sharing factorisations where that measured faster
-                    if (!persistent && policy == 5 && t == 4096 && rot == rots.back()) dflt = (int)c.size();
+                    if (!persistent && policy == 5 && t == 2816 && rot == rots.back()) dflt = (int)c.size();
                     c.push_back(sc);
                 }
         if (c.empty()) return fail(REXI_EUNSUPPORTED, "no schedule fits this truncation");

@@ -101,7 +101,7 @@ def earlier_readings(path):
     return runs
 
 
-def traffic(fetch_csv, write_csv, schedule, workload, commands, earlier=()):
+def traffic(fetch_csv, write_csv, schedule, workload, commands, earlier=(), schedule_name=None):
     GiB_KiB = float(1 << 20)
     fcal, wcal = calibration(fetch_csv, "FETCH_SIZE"), calibration(write_csv, "WRITE_SIZE")
     fscale, wscale = GiB_KiB / fcal, GiB_KiB / wcal
@@ -131,7 +131,8 @@ def traffic(fetch_csv, write_csv, schedule, workload, commands, earlier=()):
            "fetch_kib": fcal, "write_kib": wcal, "fetch_scale": fscale, "write_scale": wscale,
            "dispatch": "the largest reading among the run's torch multiply dispatches"}
     solve = {"kernel": "k_solve (fused REXI solve) class launches and k_reduce of one step",
-             "workload": workload, "schedule": schedule, "kernel_source_sha256_16": digest,
+             "workload": workload, "schedule": schedule, "schedule_name": schedule_name,
+             "kernel_source_sha256_16": digest,
              "commands": commands, "calibration": cal, "per_class": per_class,
              "traffic_bytes_per_launch": step,
              "k_solve_classes_bytes_per_launch": solve_only,
@@ -155,7 +156,7 @@ STALL_SHARES = {"active_any": "SQ_ACTIVE_INST_ANY", "active_valu": "SQ_ACTIVE_IN
                 "wait_any": "SQ_WAIT_ANY", "wait_inst_any": "SQ_WAIT_INST_ANY"}
 
 
-def counters(csv_paths, schedule, workload, commands, steps_note, clock_ghz=2.4, simds=1024):
+def counters(csv_paths, schedule, workload, commands, steps_note, clock_ghz=2.4, simds=1024, schedule_name=None):
     """Per class (mean per dispatch) and per step sums of the counters of one
     or more rocprofv3 --pmc runs (one CSV each)."""
     if isinstance(csv_paths, str):
@@ -180,7 +181,8 @@ def counters(csv_paths, schedule, workload, commands, steps_note, clock_ghz=2.4,
             if name != "dispatches":
                 step[name] += v
     out = {"kernel": "k_solve class launches and k_reduce of one step", "workload": workload,
-           "schedule": schedule, "kernel_source_sha256_16": source_digest(), "commands": commands,
+           "schedule": schedule, "schedule_name": schedule_name, "kernel_source_sha256_16": source_digest(),
+           "commands": commands,
            "per_class_mean_per_dispatch": per_class, "per_step": dict(step), "note": steps_note}
     if "SQ_INSTS_VALU_FLOPS_FP64" in step:
         out["executed_fp64_flops_per_step"] = 64.0 * step["SQ_INSTS_VALU_FLOPS_FP64"]
@@ -202,10 +204,11 @@ def counters(csv_paths, schedule, workload, commands, steps_note, clock_ghz=2.4,
     return out
 
 
-def stats(stats_csv, trace_csv, schedule, workload, command, events_ms):
+def stats(stats_csv, trace_csv, schedule, workload, command, events_ms, schedule_name=None):
     """Text summary of a kernel-trace run: per-kernel statistics and the span
     of each REXI step (first solve class start to its reduction's end)."""
-    lines = [f"# rocprofv3 kernel statistics: {workload} benchmark job (bench.py), schedule {schedule}",
+    sched = f"schedule {schedule}" + (f" ({schedule_name})" if schedule_name else "")
+    lines = [f"# rocprofv3 kernel statistics: {workload} benchmark job (bench.py), {sched}",
              "# command (on one MI355X, from /tmp with TMPDIR=/tmp):", f"#   {command}",
              "# one REXI step = one captured graph: a k_solve launch per tile class "
              "(template <elements per lane, per-term, move kind, waves, states per item>) and k_reduce;",
@@ -308,6 +311,7 @@ def main():
     c.add_argument("--out", required=True)
     for p in (t, c, k):
         p.add_argument("--schedule", type=int, required=True)
+        p.add_argument("--schedule-name", default=None, help="the schedule's name (the bench matches summaries by it)")
         p.add_argument("--workload", default="t256_fwd_adj")
         p.add_argument("--command", action="append", default=[], help="the rocprofv3 command lines (recorded)")
     x = sub.add_parser("sh")
@@ -326,16 +330,18 @@ def main():
         return
     if a.what == "stats":
         with open(a.out, "w") as f:
-            f.write(stats(a.stats, a.trace, a.schedule, a.workload, " ".join(a.command), a.events_ms))
+            f.write(stats(a.stats, a.trace, a.schedule, a.workload, " ".join(a.command), a.events_ms,
+                          a.schedule_name))
     elif a.what == "traffic":
-        solve, per_term = traffic(a.fetch, a.write, a.schedule, a.workload, a.command, earlier_readings(a.out_solve))
+        solve, per_term = traffic(a.fetch, a.write, a.schedule, a.workload, a.command, earlier_readings(a.out_solve),
+                                  a.schedule_name)
         with open(a.out_solve, "w") as f:
             json.dump(solve, f, indent=1)
         with open(a.out_per_term, "w") as f:
             json.dump(per_term, f, indent=1)
     else:
         out = counters(a.csv, a.schedule, a.workload, a.command,
-                       "per step = sum over the step's kernels of the mean per dispatch")
+                       "per step = sum over the step's kernels of the mean per dispatch", schedule_name=a.schedule_name)
         with open(a.out, "w") as f:
             json.dump(out, f, indent=1)
 

@@ -131,3 +131,18 @@ def test_counter_summary_stall_shares(tmp_path):
     assert out["icache_miss_per_hit"] == pytest.approx(1e-4)
     assert out["lds_bank_conflict_share"] == pytest.approx(0.06)
     assert out["per_class_mean_per_dispatch"]["k_solve<12, false, 1, 4, 4>"]["dispatches"] == 2
+
+
+def test_bench_uses_a_summary_only_for_its_kernel_and_schedule(tmp_path, monkeypatch):
+    b = _bench()
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    path = tmp_path / "profiles" / "s.json"
+    path.write_text(json.dumps({"kernel_source_sha256_16": "abc", "schedule_name": "fine_items10"}))
+    assert b.load_summary("s.json", "abc", "fine_items10") is not None
+    assert b.load_summary("s.json", "abc", "fine_items12") is None     # another schedule
+    assert b.load_summary("s.json", "abd", "fine_items10") is None     # another kernel source
+    assert b.load_summary("s.json", "abc") is not None                 # schedule-independent use
+    path.write_text(json.dumps({"kernel_source_sha256_16": "abc"}))    # no schedule recorded
+    assert b.load_summary("s.json", "abc", "fine_items10") is None
+    assert b.load_summary("missing.json", "abc") is None
