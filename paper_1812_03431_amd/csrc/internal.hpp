@@ -192,6 +192,7 @@ struct rexi_plan {
         int S, adjoint, buf;
         long long gen;
         hipGraphExec_t exec;
+        hipEvent_t done;  // recorded after each launch of exec
     };
     std::vector<StepGraph> graphs;
     long long graph_gen = 0;

@@ -288,8 +288,17 @@ void free_schedule(Schedule& s) {
     dev_free(s.d_groups);
 }
 
+// Each graph is destroyed only after its last launch has completed (its
+// buffers may be freed or reused right after: ensure_part, schedule and
+// stream changes).
 void drop_graphs(rexi_plan* pl) {
-    for (auto& g : pl->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& g : pl->graphs) {
+        if (g.done) {
+            (void)hipEventSynchronize(g.done);
+            (void)hipEventDestroy(g.done);
+        }
+        (void)hipGraphExecDestroy(g.exec);
+    }
     pl->graphs.clear();
     ++pl->graph_gen;
 }
@@ -360,10 +369,12 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 // The graph of one step for (S, direction, input buffer): solve launches and
 // the reduction into the other chain buffer, captured on the plan's stream.
-int step_graph(rexi_plan* pl, const Schedule& sc, int S, int adjoint, int buf, hipGraphExec_t* out) {
+int step_graph(rexi_plan* pl, const Schedule& sc, int S, int adjoint, int buf, hipGraphExec_t* out,
+               hipEvent_t* done) {
     for (auto& g : pl->graphs)
         if (g.sched == &sc && g.S == S && g.adjoint == adjoint && g.buf == buf && g.gen == pl->graph_gen) {
             *out = g.exec;
+            *done = g.done;
             return REXI_OK;
         }
     hipGraph_t graph = nullptr;
@@ -381,8 +392,15 @@ int step_graph(rexi_plan* pl, const Schedule& sc, int S, int adjoint, int buf, h
     hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e4 != hipSuccess) return hip_fail(e4, "hipGraphInstantiate");
-    pl->graphs.push_back({&sc, S, adjoint, buf, pl->graph_gen, exec});
+    hipEvent_t ev = nullptr;
+    hipError_t e5 = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e5 != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return hip_fail(e5, "hipEventCreateWithFlags");
+    }
+    pl->graphs.push_back({&sc, S, adjoint, buf, pl->graph_gen, exec, ev});
     *out = exec;
+    *done = ev;
     return REXI_OK;
 }
 
@@ -401,11 +419,13 @@ int run_steps(rexi_plan* pl, const Schedule& sc, const void* u0, void* u1, int S
         // change; with timing on, each replay is bracketed by an event pair
         for (int k = 0; k < nsteps; ++k) {
             hipGraphExec_t exec = nullptr;
-            int rc = step_graph(pl, sc, S, adjoint, cur, &exec);
+            hipEvent_t done = nullptr;
+            int rc = step_graph(pl, sc, S, adjoint, cur, &exec, &done);
             if (rc) return rc;
             REXI_HIP(timed_begin(pl, REXI_KERNEL_SOLVE, s));
             REXI_HIP(hipGraphLaunch(exec, s));
             REXI_HIP(timed_end(pl, REXI_KERNEL_SOLVE, s));
+            REXI_HIP(hipEventRecord(done, s));
             cur ^= 1;
         }
         REXI_HIP(enqueue_finish(pl, ws, cur, u1, S, adjoint, pl->sched_layout, s));
